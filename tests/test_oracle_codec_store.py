@@ -1,0 +1,184 @@
+"""Pins of the oracle's codec (against library casts), subsampling/interpolation (closed forms),
+storage accounting and the paper's worked numbers (CPU only)."""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import codec, metrics, store, yee
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_worked_numbers.json")
+
+_TORCH = {"fp16": (torch.float16, torch.int16, codec.FP16),
+          "bf16": (torch.bfloat16, torch.int16, codec.BF16),
+          "fp8_e4m3fn": (torch.float8_e4m3fn, torch.uint8, codec.FP8_E4M3FN)}
+
+
+def _torch_codes(x32: np.ndarray, name: str) -> np.ndarray:
+    dt, it, fmt = _TORCH[name]
+    t = torch.from_numpy(np.ascontiguousarray(x32, np.float32)).to(dt).view(it)
+    mask = (1 << fmt.bits) - 1
+    return t.numpy().astype(np.int64) & mask
+
+
+def _probe_values(fmt, rng):
+    """All finite values, all midpoints, midpoints +- one float32 ulp, and random values."""
+    codes, vals, _, ov = codec._table(fmt)
+    mids = (vals[:-1] + vals[1:]) / 2
+    mids32 = mids.astype(np.float32)
+    lo = np.nextafter(mids32, np.float32(-np.inf))
+    hi = np.nextafter(mids32, np.float32(np.inf))
+    top = float(np.log2(min(vals[-1], 3e38)))
+    rnd = (2.0 ** rng.uniform(-40 if fmt.exp_bits < 8 else -140, top, 200000)).astype(np.float32)
+    allv = np.concatenate([vals.astype(np.float32), mids32, lo, hi, rnd])
+    allv = allv[np.isfinite(allv) & (np.abs(allv.astype(np.float64)) < ov)]
+    return np.concatenate([allv, -allv, np.array([0.0, -0.0], np.float32)])
+
+
+@pytest.mark.parametrize("name", ["fp16", "bf16", "fp8_e4m3fn"])
+def test_encode_matches_library_cast(name):
+    rng = np.random.default_rng(0)
+    fmt = _TORCH[name][2]
+    x = _probe_values(fmt, rng)
+    mine = codec.encode(x, fmt)
+    ref = _torch_codes(x, name)
+    bad = np.nonzero(mine != ref)[0]
+    assert bad.size == 0, (x[bad[:5]], mine[bad[:5]], ref[bad[:5]])
+
+
+@pytest.mark.parametrize("name", ["fp16", "bf16", "fp8_e4m3fn"])
+def test_decode_matches_library_cast(name):
+    dt, it, fmt = _TORCH[name]
+    codes = np.arange(1 << fmt.bits)
+    mine = codec.decode(codes, fmt)
+    signed = codes.astype(np.int64)
+    if it == torch.int16:
+        signed = np.where(signed >= 32768, signed - 65536, signed)
+        t = torch.tensor(signed, dtype=torch.int16)
+    else:
+        t = torch.tensor(signed, dtype=torch.uint8)
+    ref = t.view(dt).to(torch.float64).numpy()
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(mine), fin)
+    assert np.array_equal(mine[fin], ref[fin])
+
+
+def test_fp8_overflow_rule_matches_library():
+    x = np.array([448.0, 463.9, 464.0, 464.1, 479.0, 1e4], np.float32)
+    assert np.array_equal(codec.encode(x, codec.FP8_E4M3FN), _torch_codes(x, "fp8_e4m3fn"))
+
+
+def test_fp8_scale_exponent_definition():
+    for m, e in [(448.0, 0), (449.0, 1), (224.0, -1), (224.0001, 0), (1.0, -8), (0.875, -9), (0.8751, -8),
+                 (896.0, 1), (0.0, 0), (1e-45, -126), (3e38, 120)]:
+        got = codec.fp8_scale_exponent(m)
+        assert got == e, (m, got, e)
+        if m and -126 < e < 127:
+            assert codec.FP8_MAX * 2.0 ** e >= m > codec.FP8_MAX * 2.0 ** (e - 1)
+
+
+def test_fp8_scaled_block_never_saturates_and_is_tight():
+    rng = np.random.default_rng(1)
+    for scale in (1e-30, 1e-6, 1.0, 3.0, 1e6):
+        x = (rng.standard_normal(4096) * scale).astype(np.float32)
+        codes, s = codec.encode_block(x, "fp8_e4m3fn_scaled")
+        assert math.log2(s) == int(math.log2(s))
+        v = codec.decode(codes, codec.FP8_E4M3FN)
+        assert np.all(np.isfinite(v))
+        assert np.max(np.abs(v)) <= 448.0
+        assert np.max(np.abs(x)) / s > 224.0     # the largest value lands in the top binade
+        rt = codec.decode_block(codes, s, "fp8_e4m3fn_scaled")
+        # 3 mantissa bits: relative error <= 2^-4 for values in the normal range of the block
+        big = np.abs(x) > np.max(np.abs(x)) * 2.0 ** -6
+        assert np.all(np.abs(rt[big] - x[big]) <= 2.0 ** -4 * np.abs(x[big]))
+
+
+def test_roundtrip_fp32_and_fp64_modes():
+    x = np.random.default_rng(2).standard_normal(100)
+    assert np.array_equal(codec.roundtrip_block(x, "fp64"), x)
+    assert np.array_equal(codec.roundtrip_block(x, "fp32"), x.astype(np.float32).astype(np.float64))
+
+
+# -- subsampling and interpolation --------------------------------------------
+
+def test_kept_steps_and_brackets():
+    assert store.kept_steps(10, 1) == list(range(9, -1, -1))
+    assert store.kept_steps(10, 4) == [9, 5, 1]
+    assert store.kept_steps(16, 4) == [15, 11, 7, 3]
+    assert store.kept_steps(5, 8) == [4]
+    assert store.bracket(9, 10, 4) == (9, 9, 0.0)
+    assert store.bracket(8, 10, 4) == (5, 9, 0.75)
+    assert store.bracket(0, 10, 4) == (-1, 1, 0.5)
+    assert store.bracket(2, 5, 8) == (-1, 4, 0.6)
+    for T, k in [(1000, 16), (37, 5), (8, 8), (3, 1)]:
+        assert len(store.kept_steps(T, k)) == math.ceil(T / k)
+
+
+@pytest.mark.parametrize("T,k", [(64, 4), (100, 16), (37, 5), (20, 1)])
+def test_interpolation_exact_for_linear_signals(T, k):
+    """A signal linear in n that vanishes at the anchor n = -1 is reproduced exactly."""
+    kept = {n: np.array([3.0 * (n + 1), -0.5 * (n + 1)]) for n in store.kept_steps(T, k)}
+    for n in range(T):
+        v = store.interpolate(n, T, k, kept, np.zeros(2))
+        assert np.allclose(v, [3.0 * (n + 1), -0.5 * (n + 1)], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("k,factor", [(8, 0.983), (16, 0.932), (32, 0.739)])
+def test_interpolation_sine_midpoint_factor(k, factor):
+    """Fig. 1b analogue: 136 steps per period; mid-interval the interpolant is cos(pi k / 136) of the sine."""
+    Ps = 136.0
+    T = 40 * k
+    f = lambda n: np.sin(2 * np.pi * (n + 1) / Ps + 0.3)
+    kept = {n: np.array([f(n)]) for n in store.kept_steps(T, k)}
+    for n1 in store.kept_steps(T, k)[:-1]:
+        mid = n1 - k // 2
+        v = store.interpolate(mid, T, k, kept, np.zeros(1))[0]
+        assert v == pytest.approx(math.cos(math.pi * k / Ps) * f(mid), abs=1e-12)
+    assert math.cos(math.pi * k / Ps) == pytest.approx(factor, abs=5e-4)
+
+
+def test_storage_bytes_closed_form():
+    # 128^3 with a 10-cell PML: 12 blocks of 108 x 108 per kept step
+    assert store.shell_values_per_step(128, 128, 128, 10) == 12 * 108 * 108
+    assert store.storage_bytes(128, 128, 128, 10, 1000, 1, "fp32") == (12 * 108 * 108 * 1000 * 4, 0)
+    pay, sc = store.storage_bytes(256, 256, 128, 12, 4000, 16, "fp8_e4m3fn_scaled")
+    full, _ = store.storage_bytes(256, 256, 128, 12, 4000, 1, "fp32")
+    assert full / pay == 64.0 and sc == 250 * 48
+    assert store.shell_values_per_step(20, 20, 20, 0) == 0
+
+
+# -- the paper's worked numbers --------------------------------------------
+
+def test_paper_eq1_time_step():
+    e = json.load(open(GOLDEN))["entries"][0]
+    dt = yee.courant_time_step(e["courant"], e["dx_m"], e["c_m_per_s"])
+    assert float(f"{dt:.{e['printed_digits']}g}") == e["dt_s"]
+
+
+def test_paper_period_and_steps_per_period():
+    ents = json.load(open(GOLDEN))["entries"]
+    period = ents[1]["wavelength_m"] / yee.SPEED_OF_LIGHT
+    assert float(f"{period:.3g}") == ents[1]["period_s"]
+    dt = yee.courant_time_step(0.99, 20e-9, yee.SPEED_OF_LIGHT)
+    assert round(period / dt) == ents[2]["steps_per_period"]
+
+
+def test_paper_compression_factor():
+    e = json.load(open(GOLDEN))["entries"][3]
+    assert store.compression_factor("fp8_e4m3fn_scaled", e["k"]) == e["factor"]
+    assert codec.STORAGE_BITS["fp8_e4m3fn_scaled"] == e["bits"]
+    assert store.compression_factor("fp32", 1) == 1.0
+    assert store.compression_factor("bf16", 4) == 8.0
+
+
+def test_cosine_similarity_eq2():
+    x = np.array([1.0, 2.0, -3.0])
+    assert metrics.cosine_similarity(x, 5 * x) == pytest.approx(1.0, abs=1e-15)
+    assert metrics.cosine_similarity(x, -x) == pytest.approx(-1.0, abs=1e-15)
+    assert metrics.cosine_similarity([1, 0], [0, 2]) == 0.0
+    assert metrics.cosine_similarity([1, 1], [1, 0]) == pytest.approx(1 / math.sqrt(2), rel=1e-15)
+    assert metrics.rel_l2([1.1, 2.0], [1.0, 2.0]) == pytest.approx(0.1 / math.sqrt(5), rel=1e-12)
