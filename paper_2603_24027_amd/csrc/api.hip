@@ -1,0 +1,408 @@
+// C ABI of the FDTD gradient library: validation, buffer layout, the host time
+// loops that sequence the kernels, the codec entry point and per-kernel timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fdtd.h"
+#include "common.h"
+
+using namespace fdtd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+    return h;
+}
+
+struct Plan {
+    Grid g;
+    fdtd_store_info_t info;
+    uint64_t ws_coef = 0, ws_profile = 0, ws_partials = 0, ws_staging = 0;
+    uint64_t psi_floats = 0;
+    int per_step = 0;
+    int64_t src_volume = 0;
+    std::vector<float> coef;   // 12 P floats
+    uint64_t hash = 0;
+};
+
+bool box_inside_interior(const int32_t lo[3], const int32_t hi[3], const int n[3], int P) {
+    for (int d = 0; d < 3; ++d)
+        if (lo[d] < P || hi[d] > n[d] - P || lo[d] >= hi[d]) return false;
+    return true;
+}
+
+// CPML tables indexed by the slab coordinate i' in [0, 2P).  Depth from the
+// interior boundary: E nodes (x = i) and H nodes (x = i + 1/2); the low slab
+// has i' = i, the high slab i' = i - (n - 2P), so the depth depends on i' only.
+void cpml_tables(const fdtd_problem_t* p, double dt, std::vector<float>& coef) {
+    const int P = p->pml;
+    coef.assign(12 * (size_t)P, 0.0f);
+    const double m = p->pml_order;
+    const double sig_max = p->pml_sigma_scale * 0.8 * (m + 1.0);
+    for (int node = 0; node < 2; ++node) {
+        for (int s = 0; s < 2 * P; ++s) {
+            double depth;
+            if (node == 0) depth = s < P ? (double)(P - s) : (double)(s - P) + 0.5;
+            else depth = s < P ? (double)(P - s) - 0.5 : (double)(s - P) + 1.0;
+            const double rho = depth / P;
+            const double rm = std::pow(rho, m);
+            const double sigma = sig_max * rm;
+            const double kappa = 1.0 + (p->pml_kappa_max - 1.0) * rm;
+            const double alpha = p->pml_alpha_max * (1.0 - rho);
+            const double b = std::exp(-(sigma / kappa + alpha) * dt);
+            const double a = sigma > 0.0 ? sigma * (b - 1.0) / (sigma * kappa + kappa * kappa * alpha) : 0.0;
+            float* base = coef.data() + (size_t)node * 6 * P;
+            base[s] = (float)b;
+            base[2 * P + s] = (float)a;
+            base[4 * P + s] = (float)(1.0 / kappa);
+        }
+    }
+}
+
+int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
+    if (!p || !cfg) return fail(FDTD_EINVAL, "problem and store config must not be NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(FDTD_EINVAL, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+    if (p->ny > 4 * 65535 || p->nz > 65535 || (int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 36)
+        return fail(FDTD_EINVAL, "grid too large for this build");
+    if (p->steps < 1) return fail(FDTD_EINVAL, "steps must be >= 1 (got %d)", p->steps);
+    if (p->pml < 0 || p->pml > FDTD_MAX_PML) return fail(FDTD_EINVAL, "pml must be in [0, %d]", FDTD_MAX_PML);
+    const int n[3] = {p->nx, p->ny, p->nz};
+    for (int d = 0; d < 3; ++d)
+        if (2 * p->pml >= n[d]) return fail(FDTD_EINVAL, "2 * pml must be smaller than every extent");
+    if (p->boundary != 0 && p->boundary != 1) return fail(FDTD_EINVAL, "boundary must be 0 or 1");
+    if (p->boundary == 1 && p->pml != 0) return fail(FDTD_EINVAL, "a periodic grid has no PML (pml must be 0)");
+    if (!(std::isfinite(p->courant) && p->courant > 0.0 && p->courant <= 1.0))
+        return fail(FDTD_ECFL, "Courant number %g outside (0, 1]", p->courant);
+    if (p->pml_order < 1 || !(p->pml_sigma_scale >= 0.0) || !(p->pml_kappa_max >= 1.0) ||
+        !(p->pml_alpha_max >= 0.0) || !std::isfinite(p->pml_sigma_scale) || !std::isfinite(p->pml_kappa_max) ||
+        !std::isfinite(p->pml_alpha_max))
+        return fail(FDTD_EINVAL, "invalid PML grading parameters");
+    if (p->src_comp < 0 || p->src_comp > 2) return fail(FDTD_EINVAL, "src_comp must be 0, 1 or 2");
+    if (!p->src_wave || !p->src_profile) return fail(FDTD_EINVAL, "source signal and profile must not be NULL");
+    if (!box_inside_interior(p->src_lo, p->src_hi, n, p->pml))
+        return fail(FDTD_EREGION, "source box must be non-empty and inside the interior");
+    if (!box_inside_interior(p->det_lo, p->det_hi, n, p->pml))
+        return fail(FDTD_EREGION, "detector box must be non-empty and inside the interior");
+    if (!box_inside_interior(p->des_lo, p->des_hi, n, p->pml))
+        return fail(FDTD_EREGION, "design box must be non-empty and inside the interior");
+    if (cfg->dtype < FDTD_STORE_FP32 || cfg->dtype > FDTD_STORE_FP8_E4M3_SCALED)
+        return fail(FDTD_ESTORE, "unknown storage type %d", cfg->dtype);
+    if (cfg->k < 1) return fail(FDTD_ESTORE, "subsampling k must be >= 1 (got %d)", cfg->k);
+
+    const int P = p->pml;
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const double dt = p->courant / std::sqrt(3.0);   // Eq. 1 with dx = c = 1
+    Grid& g = pl->g;
+    std::memset(&g, 0, sizeof g);
+    g.nx = p->nx; g.ny = p->ny; g.nz = p->nz; g.P = P;
+    g.periodic = p->boundary;
+    g.mx = p->nx - 2 * P; g.my = p->ny - 2 * P; g.mz = p->nz - 2 * P;
+    g.N = N;
+    g.dt = (float)dt;
+    g.slab[0] = 2LL * P * p->ny * p->nz;
+    g.slab[1] = 2LL * P * p->nx * p->nz;
+    g.slab[2] = 2LL * P * p->nx * p->ny;
+    g.psi_off[0] = 0;
+    g.psi_off[1] = 4 * g.slab[0];
+    g.psi_off[2] = 4 * (g.slab[0] + g.slab[1]);
+    g.psi_total = 4 * (g.slab[0] + g.slab[1] + g.slab[2]);
+    g.src_comp = p->src_comp;
+    for (int d = 0; d < 3; ++d) {
+        g.src_lo[d] = p->src_lo[d]; g.src_hi[d] = p->src_hi[d];
+        g.det_lo[d] = p->det_lo[d]; g.det_hi[d] = p->det_hi[d];
+        g.des_lo[d] = p->des_lo[d]; g.des_hi[d] = p->des_hi[d];
+    }
+    g.dtype = cfg->dtype;
+    const int64_t vps = P > 0 ? 4LL * ((int64_t)g.my * g.mz + (int64_t)g.mx * g.mz + (int64_t)g.mx * g.my) : 0;
+    g.vps = vps;
+    const uint64_t vbytes = (uint64_t)storage_bytes(cfg->dtype);
+    const uint64_t slices = ((uint64_t)p->steps + cfg->k - 1) / cfg->k;
+    g.slice_stride = (long long)align_up(vps * vbytes, 256);
+    g.scale_off = (long long)(slices * (uint64_t)g.slice_stride);
+    g.dbx0 = p->det_lo[0] / BX; g.dnbx = (p->det_hi[0] - 1) / BX - g.dbx0 + 1;
+    g.dby0 = p->det_lo[1] / BY; g.dnby = (p->det_hi[1] - 1) / BY - g.dby0 + 1;
+    g.dbz0 = p->det_lo[2];      g.dnbz = p->det_hi[2] - p->det_lo[2];
+    pl->per_step = g.dnbx * g.dnby * g.dnbz;
+    pl->psi_floats = (uint64_t)g.psi_total;
+    pl->src_volume = (int64_t)(p->src_hi[0] - p->src_lo[0]) * (p->src_hi[1] - p->src_lo[1]) *
+                     (p->src_hi[2] - p->src_lo[2]);
+
+    fdtd_store_info_t& in = pl->info;
+    std::memset(&in, 0, sizeof in);
+    in.cells = (uint64_t)N;
+    in.slices = slices;
+    in.values_per_slice = (uint64_t)vps;
+    in.payload_bytes = slices * (uint64_t)vps * vbytes;
+    in.scale_bytes = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? slices * 12 * 4 : 0;
+    in.store_bytes = std::max<uint64_t>(256, (uint64_t)g.scale_off + align_up(in.scale_bytes, 256));
+    in.fields_bytes = 6ull * (uint64_t)N * 4;
+    in.psi_bytes = std::max<uint64_t>(256, pl->psi_floats * 4);
+    in.adj_psi_bytes = std::max<uint64_t>(512, 2 * pl->psi_floats * 4);
+    pl->ws_coef = 0;
+    pl->ws_profile = align_up(12ull * P * 4, 256);
+    pl->ws_partials = pl->ws_profile + align_up((uint64_t)pl->src_volume * 4, 256);
+    pl->ws_staging = pl->ws_partials + align_up((uint64_t)p->steps * pl->per_step * 8, 256);
+    const uint64_t staging = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? align_up((uint64_t)vps * 4, 256) : 0;
+    in.workspace_bytes = pl->ws_staging + staging;
+    in.design_cells = (uint64_t)(p->des_hi[0] - p->des_lo[0]) * (p->des_hi[1] - p->des_lo[1]) *
+                      (p->des_hi[2] - p->des_lo[2]);
+
+    cpml_tables(p, dt, pl->coef);
+
+    uint64_t h = 1469598103934665603ull;
+    const int32_t ints[] = {p->nx, p->ny, p->nz, p->pml, p->steps, p->boundary, p->pml_order, p->src_comp,
+                            p->src_lo[0], p->src_lo[1], p->src_lo[2], p->src_hi[0], p->src_hi[1], p->src_hi[2],
+                            p->det_lo[0], p->det_lo[1], p->det_lo[2], p->det_hi[0], p->det_hi[1], p->det_hi[2],
+                            p->des_lo[0], p->des_lo[1], p->des_lo[2], p->des_hi[0], p->des_hi[1], p->des_hi[2]};
+    const double dbl[] = {p->courant, p->pml_sigma_scale, p->pml_kappa_max, p->pml_alpha_max};
+    h = fnv1a(h, ints, sizeof ints);
+    h = fnv1a(h, dbl, sizeof dbl);
+    h = fnv1a(h, p->src_wave, (size_t)p->steps * 4);
+    h = fnv1a(h, p->src_profile, (size_t)pl->src_volume * 4);
+    pl->hash = h;
+    return FDTD_OK;
+}
+
+Interp interp_for(int n, int T, int k) {
+    Interp q;
+    if ((T - 1 - n) % k == 0) {
+        q.j0 = -1; q.j1 = (T - 1 - n) / k; q.w0 = 0.0f; q.w1 = 1.0f;
+        return q;
+    }
+    const int j1 = (T - 1 - n) / k;
+    const int n1 = T - 1 - j1 * k;
+    int n0 = n1 - k, j0 = j1 + 1;
+    if (n0 < 0) { n0 = -1; j0 = -1; }
+    const double w = (double)(n - n0) / (double)(n1 - n0);
+    q.j0 = j0; q.j1 = j1;
+    q.w0 = (float)(1.0 - w);
+    q.w1 = (float)w;
+    return q;
+}
+
+int check_hip(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(FDTD_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return FDTD_OK;
+}
+
+// ---- per-kernel timing ------------------------------------------------------
+const char* kKindNames[K_NUM_KINDS] = {"fill", "fwd_h", "fwd_e", "rec_quant", "loss_final",
+                                       "rev_init", "rev_e", "rev_h", "scale_grad", "codec"};
+constexpr size_t kMaxTimedLaunches = 1 << 16;
+
+struct Timing {
+    std::mutex mu;
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;      // 2 events per timed launch
+    std::vector<int> kinds;            // kind of each timed launch
+    size_t used = 0;
+} g_timing;
+
+}  // namespace
+
+namespace fdtd {
+bool timing_acquire(int kind, hipEvent_t* start, hipEvent_t* stop) {
+    if (!g_timing.enabled) return false;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (g_timing.used >= kMaxTimedLaunches) return false;
+    while (g_timing.pool.size() < 2 * (g_timing.used + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return false;
+        g_timing.pool.push_back(e);
+    }
+    *start = g_timing.pool[2 * g_timing.used];
+    *stop = g_timing.pool[2 * g_timing.used + 1];
+    if (g_timing.kinds.size() <= g_timing.used) g_timing.kinds.resize(g_timing.used + 1);
+    g_timing.kinds[g_timing.used] = kind;
+    ++g_timing.used;
+    return true;
+}
+}  // namespace fdtd
+
+extern "C" {
+
+int store_config(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, fdtd_store_info_t* info) {
+    if (!info) return fail(FDTD_EINVAL, "info must not be NULL");
+    Plan pl;
+    int rc = make_plan(prob, cfg, &pl);
+    if (rc) return rc;
+    *info = pl.info;
+    return FDTD_OK;
+}
+
+int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const float* eps, float* fields,
+                 float* psi, void* store, void* workspace, double* loss, double* loss_series,
+                 fdtd_record_t* rec, void* stream) {
+    Plan pl;
+    int rc = make_plan(prob, cfg, &pl);
+    if (rc) return rc;
+    if (!eps || !fields || !psi || !store || !workspace || !loss || !rec)
+        return fail(FDTD_EINVAL, "fdtd_forward: eps, fields, psi, store, workspace, loss and rec must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    Grid g = pl.g;
+    g.coef = (const float*)(ws + pl.ws_coef);
+    g.src_profile = (const float*)(ws + pl.ws_profile);
+    double* partials = (double*)(ws + pl.ws_partials);
+    float* staging = (float*)(ws + pl.ws_staging);
+
+    // coefficient tables and source profile: staged through a host buffer that
+    // outlives the (pageable, staged-before-return) asynchronous copy
+    static thread_local std::vector<char> host;
+    host.assign(pl.ws_partials, 0);
+    std::memcpy(host.data() + pl.ws_coef, pl.coef.data(), pl.coef.size() * 4);
+    std::memcpy(host.data() + pl.ws_profile, prob->src_profile, (size_t)pl.src_volume * 4);
+    if (hipMemcpyAsync(ws, host.data(), pl.ws_partials, hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail(FDTD_EHIP, "fdtd_forward: upload of coefficient tables failed");
+
+    const int64_t N = g.N;
+    float* E = fields;
+    float* H = fields + 3 * N;
+    launch_fill(fields, 6 * N, 0.0f, s);
+    launch_fill(psi, (long long)pl.psi_floats, 0.0f, s);
+    const int T = prob->steps, k = cfg->k;
+    const bool fp8 = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED && g.vps > 0;
+    for (int n = 0; n < T; ++n) {
+        const int slice = ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1;
+        launch_fwd_h(g, E, H, psi, store, staging, slice, s);
+        launch_fwd_e(g, E, H, eps, psi, prob->src_wave[n], partials + (int64_t)n * pl.per_step, s);
+        if (slice >= 0 && fp8) launch_rec_quant(g, staging, store, slice, s);
+    }
+    launch_loss_final(partials, T, pl.per_step, loss, loss_series, s);
+    rc = check_hip("fdtd_forward");
+    if (rc) return rc;
+    rec->problem_hash = pl.hash;
+    rec->dtype = cfg->dtype;
+    rec->k = cfg->k;
+    rec->steps = T;
+    rec->consumed = 0;
+    return FDTD_OK;
+}
+
+int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const float* eps, float* fields,
+                  const void* store, void* workspace, float* adj_fields, float* adj_psi,
+                  const double* grad_scale, double* grad_eps, fdtd_record_t* rec, void* stream) {
+    Plan pl;
+    int rc = make_plan(prob, cfg, &pl);
+    if (rc) return rc;
+    if (!rec) return fail(FDTD_EINVAL, "fdtd_backward: rec must not be NULL");
+    if (rec->problem_hash != pl.hash || rec->dtype != cfg->dtype || rec->k != cfg->k || rec->steps != prob->steps)
+        return fail(FDTD_ESTORE, "fdtd_backward: the record belongs to a different problem or store config");
+    if (rec->consumed)
+        return fail(FDTD_ESTATE, "fdtd_backward: record already consumed (the fields were reversed)");
+    if (!eps || !fields || !store || !workspace || !adj_fields || !adj_psi || !grad_eps)
+        return fail(FDTD_EINVAL, "fdtd_backward: device pointers must not be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    Grid g = pl.g;
+    g.coef = (const float*)(ws + pl.ws_coef);
+    g.src_profile = (const float*)(ws + pl.ws_profile);
+
+    const int T = prob->steps, k = cfg->k;
+    float* psi_buf[2] = {adj_psi, adj_psi + pl.psi_floats};
+    launch_fill(adj_psi, 2 * (long long)pl.psi_floats, 0.0f, s);
+    launch_fill_f64(grad_eps, (long long)pl.info.design_cells, 0.0, s);
+    launch_rev_init(g, fields, adj_fields, store, interp_for(T - 1, T, k), s);
+    int cur = 0;
+    for (int n = T - 1; n >= 0; --n) {
+        launch_rev_e(g, fields, eps, adj_fields, psi_buf[cur], psi_buf[1 - cur], store, interp_for(n, T, k),
+                     prob->src_wave[n], grad_eps, s);
+        const Interp qh = n >= 1 ? interp_for(n - 1, T, k) : Interp{-1, 0, 0.0f, 0.0f};
+        launch_rev_h(g, fields, adj_fields, psi_buf[cur], psi_buf[1 - cur], store, qh, n >= 1, n >= 1, s);
+        cur = 1 - cur;
+    }
+    if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, s);
+    rc = check_hip("fdtd_backward");
+    if (rc) return rc;
+    rec->consumed = 1;
+    return FDTD_OK;
+}
+
+int fdtd_codec_roundtrip(int32_t dtype, const float* values, int64_t n_blocks, int64_t block_len, void* codes,
+                         float* scales, float* decoded, void* stream) {
+    if (dtype < FDTD_STORE_FP32 || dtype > FDTD_STORE_FP8_E4M3_SCALED)
+        return fail(FDTD_ESTORE, "unknown storage type %d", dtype);
+    if (n_blocks < 0 || block_len < 0 || n_blocks > 0x7fffffff)
+        return fail(FDTD_EINVAL, "fdtd_codec_roundtrip: bad block count or length");
+    if (n_blocks == 0 || block_len == 0) return FDTD_OK;
+    if (!values || !codes || !decoded || (dtype == FDTD_STORE_FP8_E4M3_SCALED && !scales))
+        return fail(FDTD_EINVAL, "fdtd_codec_roundtrip: NULL buffer");
+    launch_codec_roundtrip(dtype, values, n_blocks, block_len, codes, scales, decoded, (hipStream_t)stream);
+    return check_hip("fdtd_codec_roundtrip");
+}
+
+int fdtd_timing_enable(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    g_timing.enabled = enable != 0;
+    g_timing.used = 0;
+    return FDTD_OK;
+}
+
+int fdtd_timing_read(fdtd_kernel_time_t* out, int32_t max_kinds) {
+    if (!out || max_kinds < 0) return fail(FDTD_EINVAL, "fdtd_timing_read: bad output buffer");
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    double total[K_NUM_KINDS] = {0};
+    uint64_t count[K_NUM_KINDS] = {0};
+    for (size_t t = 0; t < g_timing.used; ++t) {
+        if (hipEventSynchronize(g_timing.pool[2 * t + 1]) != hipSuccess)
+            return fail(FDTD_EHIP, "fdtd_timing_read: event synchronisation failed");
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, g_timing.pool[2 * t], g_timing.pool[2 * t + 1]) != hipSuccess)
+            return fail(FDTD_EHIP, "fdtd_timing_read: elapsed time unavailable");
+        total[g_timing.kinds[t]] += ms;
+        count[g_timing.kinds[t]] += 1;
+    }
+    int filled = 0;
+    for (int kd = 0; kd < K_NUM_KINDS && filled < max_kinds; ++kd) {
+        if (!count[kd]) continue;
+        std::memset(&out[filled], 0, sizeof out[filled]);
+        std::snprintf(out[filled].name, sizeof out[filled].name, "%s", kKindNames[kd]);
+        out[filled].launches = count[kd];
+        out[filled].total_ms = total[kd];
+        ++filled;
+    }
+    return filled;
+}
+
+const char* fdtd_strerror(int code) {
+    switch (code) {
+        case FDTD_OK: return "ok";
+        case FDTD_EINVAL: return "invalid argument";
+        case FDTD_ECFL: return "Courant number outside (0, 1]";
+        case FDTD_EREGION: return "box outside the interior";
+        case FDTD_ESTORE: return "invalid store configuration or mismatched record";
+        case FDTD_ESTATE: return "record already consumed";
+        case FDTD_EHIP: return "HIP runtime error";
+        case FDTD_ENONFINITE: return "non-finite loss";
+        default: return "unknown error";
+    }
+}
+
+const char* fdtd_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,303 @@
+// Shared device-side definitions of the FDTD gradient library (gfx950).
+//
+// Grid arrays are float32 structure-of-arrays, x fastest; the six field
+// components of one buffer are [Ex | Ey | Ez | Hx | Hy | Hz], N cells each.
+//
+// Curl terms, numbered t = 0..5 for both halves of a step
+// (component c, axis d, sign s, source field f):
+//   H half (curl E, forward differences):
+//     0 (Hx, y, +, Ez)  1 (Hx, z, -, Ey)  2 (Hy, z, +, Ex)
+//     3 (Hy, x, -, Ez)  4 (Hz, x, +, Ey)  5 (Hz, y, -, Ex)
+//   E half (curl H, backward differences):
+//     0 (Ex, y, +, Hz)  1 (Ex, z, -, Hy)  2 (Ey, z, +, Hx)
+//     3 (Ey, x, -, Hz)  4 (Ez, x, +, Hy)  5 (Ez, y, -, Hx)
+// so axis x carries terms 3 and 4, axis y terms 0 and 5, axis z terms 1 and 2.
+//
+// Convolutional-PML auxiliaries live only in the slabs [0, P) and [n-P, n) of
+// their axis.  Slab of axis d, slab coordinate i' in [0, 2P):
+//   i' = i for i < P, i' = i - (n - 2P) for i >= n - P.
+// Within the PML buffer each axis owns four slab-sized arrays
+//   [H term a, H term b, E term a, E term b] with (a, b) = (3, 4) for x,
+//   (0, 5) for y and (1, 2) for z;  slab layouts (x fastest):
+//   x: i' + 2P (j + ny k),  y: i + nx (j' + 2P k),  z: i + nx (j + ny k').
+// The CPML coefficients depend on i' only (same thickness on every face),
+// so one table of 2P entries per node type serves all three axes:
+//   coef = [bE | aE | kinvE | bH | aH | kinvH], 2P floats each.
+#pragma once
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdtd {
+
+constexpr int BX = 64;   // threads along x (one wavefront per x segment)
+constexpr int BY = 4;    // rows per block
+
+struct Grid {
+    int nx, ny, nz, P;
+    int periodic;
+    int mx, my, mz;          // interior extents n - 2P
+    long long N;             // cells
+    float dt;
+    long long psi_off[3];    // start of each axis' four slab arrays in a PML buffer (floats)
+    long long slab[3];       // slab size per axis (floats)
+    long long psi_total;     // floats in one PML buffer
+    const float* coef;       // device coefficient table (6 * 2P floats)
+    // source
+    int src_comp;
+    int src_lo[3], src_hi[3];
+    const float* src_profile;
+    // detector and design boxes
+    int det_lo[3], det_hi[3];
+    int des_lo[3], des_hi[3];
+    // interface store
+    int dtype;
+    long long vps;           // values per kept step
+    long long slice_stride;  // bytes between kept steps in the store
+    long long scale_off;     // byte offset of the FP8 scale table in the store
+    // detector-loss partials (forward): blocks intersecting the detector
+    int dbx0, dby0, dbz0, dnbx, dnby, dnbz;
+};
+
+// ----------------------------------------------------------------------------
+// Codec (bit-width reduction of recorded values).  All encoders round to
+// nearest, ties to even, as the IEEE default.
+// ----------------------------------------------------------------------------
+
+__host__ __device__ inline uint32_t f2u(float x) {
+    union { float f; uint32_t u; } v; v.f = x; return v.u;
+}
+__host__ __device__ inline float u2f(uint32_t u) {
+    union { float f; uint32_t u; } v; v.u = u; return v.f;
+}
+
+__host__ __device__ inline uint16_t enc_bf16(float x) {
+    uint32_t u = f2u(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x0040u);   // quiet NaN
+    uint32_t lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7fffu + lsb) >> 16);
+}
+__host__ __device__ inline float dec_bf16(uint16_t h) { return u2f(((uint32_t)h) << 16); }
+
+// IEEE binary16 from float32, round to nearest even (software, exact).
+__host__ __device__ inline uint16_t enc_fp16(float x) {
+    uint32_t u = f2u(x);
+    uint32_t sign = (u >> 16) & 0x8000u;
+    uint32_t a = u & 0x7fffffffu;
+    if (a > 0x7f800000u) return (uint16_t)(sign | 0x7e00u);          // NaN
+    if (a >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);         // >= 65520 rounds to inf
+    int e = (int)(a >> 23) - 127;
+    if (e < -14) {                                                   // half subnormal (or zero)
+        // value = q * 2^-24, q = rint(|x| * 2^24)
+        float s = u2f(a) * 16777216.0f;                              // exact scaling
+        float q = rintf(s);
+        return (uint16_t)(sign | (uint32_t)q);                       // q = 1024 -> min normal
+    }
+    uint32_t mant = a & 0x7fffffu;
+    uint32_t code = ((uint32_t)(e + 15) << 10) | (mant >> 13);
+    uint32_t rem = mant & 0x1fffu;
+    if (rem > 0x1000u || (rem == 0x1000u && (code & 1u))) code += 1u;
+    return (uint16_t)(sign | code);
+}
+__host__ __device__ inline float dec_fp16(uint16_t h) {
+    uint32_t sign = ((uint32_t)h & 0x8000u) << 16;
+    uint32_t e = (h >> 10) & 0x1fu, m = h & 0x3ffu;
+    if (e == 0) {
+        float v = (float)m * 5.9604644775390625e-08f;                // m * 2^-24, exact
+        return u2f(f2u(v) | sign);
+    }
+    if (e == 31) return u2f(sign | 0x7f800000u | (m << 13));
+    return u2f(sign | ((e - 15 + 127) << 23) | (m << 13));
+}
+
+// OCP FP8 E4M3 (bias 7, max 448, S.1111.111 = NaN, no infinity).  Values past
+// the rounding threshold of 448 map to NaN (non-saturating); the scaled
+// recorder never produces them.
+__host__ __device__ inline uint8_t enc_e4m3(float x) {
+    uint32_t u = f2u(x);
+    uint32_t sign = (u >> 24) & 0x80u;
+    uint32_t a = u & 0x7fffffffu;
+    if (a > 0x7f800000u) return (uint8_t)(sign | 0x7fu);
+    float af = u2f(a);
+    if (af > 464.0f) return (uint8_t)(sign | 0x7fu);
+    if (af < 0.015625f) {                                            // below 2^-6: subnormal
+        float q = rintf(af * 512.0f);                                // value = q * 2^-9
+        return (uint8_t)(sign | (uint32_t)q);                        // q = 8 -> min normal
+    }
+    int e = (int)(a >> 23) - 127;
+    uint32_t mant = a & 0x7fffffu;
+    uint32_t code = ((uint32_t)(e + 7) << 3) | (mant >> 20);
+    uint32_t rem = mant & 0xfffffu;
+    if (rem > 0x80000u || (rem == 0x80000u && (code & 1u))) code += 1u;
+    return (uint8_t)(sign | code);
+}
+__host__ __device__ inline float dec_e4m3(uint8_t c) {
+    uint32_t sign = ((uint32_t)c & 0x80u) << 24;
+    uint32_t e = (c >> 3) & 0xfu, m = c & 7u;
+    if (e == 15 && m == 7) return u2f(sign | 0x7fc00000u);
+    float v = (e == 0) ? (float)m * 0.001953125f                     // m * 2^-9
+                       : u2f(((e - 7 + 127) << 23) | (m << 20));
+    return u2f(f2u(v) | sign);
+}
+
+// Power-of-two scale exponent: smallest e with 448 * 2^e >= m, clamped to [-126, 127].
+__host__ __device__ inline int fp8_scale_exp(float m) {
+    if (!(m > 0.0f)) return 0;
+    uint32_t u = f2u(m);
+    int E;
+    uint32_t mant;
+    if ((u >> 23) == 0) {                                            // float32 subnormal
+        // m = mant * 2^-149; normalise
+        uint32_t x = u & 0x7fffffu;
+        int sh = 0;
+        while (!(x & 0x800000u)) { x <<= 1; ++sh; }
+        E = -126 - sh;                                               // m = 1.f * 2^E
+        mant = x & 0x7fffffu;
+    } else {
+        E = (int)(u >> 23) - 127;
+        mant = u & 0x7fffffu;
+    }
+    // m = 1.f * 2^E with 1.f in [1, 2), and 448 = 1.75 * 2^8, so
+    //   448 * 2^e >= m  <=>  2^(e - E + 8) >= 1.f / 1.75, a ratio in [4/7, 8/7).
+    // The smallest such e is E - 8 when 1.f <= 1.75 (mantissa <= 0x600000), else E - 7.
+    int e = (mant > 0x600000u) ? E - 7 : E - 8;
+    if (e < -126) e = -126;
+    if (e > 127) e = 127;
+    return e;
+}
+
+__host__ __device__ inline float pow2f(int e) {   // 2^e for e in [-126, 127]
+    return u2f((uint32_t)(e + 127) << 23);
+}
+
+inline __host__ __device__ int storage_bytes(int dtype) {
+    return dtype == 0 ? 4 : (dtype == 3 ? 1 : 2);
+}
+
+// Decode one stored value (FP8 needs its block scale).
+__device__ inline float load_code(const void* store, long long byte_slice, long long off, int dtype, float scale) {
+    const char* base = (const char*)store + byte_slice;
+    switch (dtype) {
+        case 0: return ((const float*)base)[off];
+        case 1: return dec_fp16(((const uint16_t*)base)[off]);
+        case 2: return dec_bf16(((const uint16_t*)base)[off]);
+        default: return dec_e4m3(((const uint8_t*)base)[off]) * scale;
+    }
+}
+
+__device__ inline void store_code(void* store, long long byte_slice, long long off, int dtype, float v) {
+    char* base = (char*)store + byte_slice;
+    switch (dtype) {
+        case 0: ((float*)base)[off] = v; break;
+        case 1: ((uint16_t*)base)[off] = enc_fp16(v); break;
+        case 2: ((uint16_t*)base)[off] = enc_bf16(v); break;
+        default: break;   // FP8 goes through the staging buffer and the quantiser kernel
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Interface shell geometry: 12 blocks per kept step, in this order
+//   0,1  x-low  (Hy, Hz) at i = P-1      [k][j]
+//   2,3  y-low  (Hz, Hx) at j = P-1      [k][i]
+//   4,5  z-low  (Hx, Hy) at k = P-1      [j][i]
+//   6,7  x-high (Ey, Ez) at i = nx-P     [k][j]
+//   8,9  y-high (Ez, Ex) at j = ny-P     [k][i]
+//   10,11 z-high (Ex, Ey) at k = nz-P    [j][i]
+// each over the interior extent of the other two axes.
+// ----------------------------------------------------------------------------
+__host__ __device__ inline long long block_offset(const Grid& g, int b) {
+    long long ax = (long long)g.my * g.mz, ay = (long long)g.mx * g.mz, az = (long long)g.mx * g.my;
+    long long face[6] = {0, 2 * ax, 2 * ax + 2 * ay, 2 * (ax + ay + az), 2 * (ax + ay + az) + 2 * ax,
+                         2 * (ax + ay + az) + 2 * ax + 2 * ay};
+    long long area[3] = {ax, ay, az};
+    int f = b >> 1;
+    return face[f] + (b & 1) * area[f % 3];
+}
+
+__host__ __device__ inline long long block_len(const Grid& g, int b) {
+    int f = (b >> 1) % 3;
+    return f == 0 ? (long long)g.my * g.mz : (f == 1 ? (long long)g.mx * g.mz : (long long)g.mx * g.my);
+}
+
+// Per-step parameters of the interpolating reinjection: v = w0 * slice(j0) + w1 * slice(j1);
+// j0 < 0 denotes the exact zero anchor before the first step.
+struct Interp {
+    int j0, j1;
+    float w0, w1;
+};
+
+__device__ inline float shell_value(const Grid& g, const void* store, const Interp& q, int b, long long off) {
+    long long o = block_offset(g, b) + off;
+    const float* scales = (const float*)((const char*)store + g.scale_off);
+    float s1 = g.dtype == 3 ? scales[q.j1 * 12 + b] : 1.0f;
+    float v = q.w1 * load_code(store, q.j1 * g.slice_stride, o, g.dtype, s1);
+    if (q.j0 >= 0) {
+        float s0 = g.dtype == 3 ? scales[q.j0 * 12 + b] : 1.0f;
+        v += q.w0 * load_code(store, q.j0 * g.slice_stride, o, g.dtype, s0);
+    }
+    return v;
+}
+
+__device__ inline bool in_box(int i, int j, int k, const int lo[3], const int hi[3]) {
+    return i >= lo[0] && i < hi[0] && j >= lo[1] && j < hi[1] && k >= lo[2] && k < hi[2];
+}
+
+// Neighbour at +1 along an axis (zero outside, or wrapped)
+__device__ inline float nb_plus(const float* f, long long idx, int i, int n, long long stride, int periodic) {
+    if (i + 1 < n) return f[idx + stride];
+    return periodic ? f[idx - (long long)(n - 1) * stride] : 0.0f;
+}
+__device__ inline float nb_minus(const float* f, long long idx, int i, int n, long long stride, int periodic) {
+    if (i > 0) return f[idx - stride];
+    return periodic ? f[idx + (long long)(n - 1) * stride] : 0.0f;
+}
+
+__device__ inline int slab_coord(int i, int n, int P) {   // -1 outside the slab
+    if (i < P) return i;
+    if (i >= n - P) return i - (n - 2 * P);
+    return -1;
+}
+
+// ----------------------------------------------------------------------------
+// Launches.  With per-kernel timing on, each launch carries a start and stop
+// event on its own dispatch (hipExtLaunchKernelGGL), so the recorded interval
+// is the kernel's execution and no extra packet enters the stream.
+// ----------------------------------------------------------------------------
+enum KernelKind {
+    K_FILL = 0, K_FWD_H, K_FWD_E, K_REC_QUANT, K_LOSS_FINAL, K_REV_INIT, K_REV_E, K_REV_H, K_SCALE_GRAD,
+    K_CODEC, K_NUM_KINDS
+};
+
+// Defined in api.hip: hands out an event pair when timing is enabled.
+bool timing_acquire(int kind, hipEvent_t* start, hipEvent_t* stop);
+
+template <typename Kernel, typename... Args>
+inline void launch_kernel(int kind, Kernel kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+    hipEvent_t a, b;
+    if (timing_acquire(kind, &a, &b))
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
+// Launch wrappers (defined with the kernels)
+void launch_fill(float* p, long long n, float v, hipStream_t s);
+void launch_fill_f64(double* p, long long n, double v, hipStream_t s);
+void launch_fwd_h(const Grid& g, const float* E, float* H, float* psi, void* store, float* staging,
+                  int slice, hipStream_t s);
+void launch_fwd_e(const Grid& g, float* E, const float* H, const float* eps, float* psi, float wave,
+                  double* partials, hipStream_t s);
+void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s);
+void launch_loss_final(const double* partials, int steps, int per_step, double* loss, double* series,
+                       hipStream_t s);
+void launch_rev_init(const Grid& g, float* fields, float* adj, const void* store, Interp q, hipStream_t s);
+void launch_rev_e(const Grid& g, float* fields, const float* eps, float* adj, const float* psi_in,
+                  float* psi_out, const void* store, Interp q, float wave, double* grad, hipStream_t s);
+void launch_rev_h(const Grid& g, float* fields, float* adj, const float* psi_in, float* psi_out,
+                  const void* store, Interp q, int inject, int seed, hipStream_t s);
+void launch_scale_grad(double* grad, long long n, const double* scale, hipStream_t s);
+void launch_codec_roundtrip(int dtype, const float* values, long long n_blocks, long long block_len,
+                            void* codes, float* scales, float* decoded, hipStream_t s);
+
+}  // namespace fdtd

@@ -1,0 +1,209 @@
+"""Python binding of the HIP FDTD gradient library: buffers, calls, and a torch.autograd.Function.
+
+Every step of the method runs in the library's kernels; this module only
+builds the C structs, allocates device memory through torch, and passes
+pointers and the current HIP stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FdtdProblem, FdtdRecord, FdtdStoreCfg, FdtdStoreInfo, check, load
+
+STORE_DTYPES = {
+    "fp32": _lib.STORE_FP32,
+    "fp16": _lib.STORE_FP16,
+    "bf16": _lib.STORE_BF16,
+    "fp8_e4m3_scaled": _lib.STORE_FP8_E4M3_SCALED,
+}
+STORAGE_BITS = {"fp32": 32, "fp16": 16, "bf16": 16, "fp8_e4m3_scaled": 8}
+
+
+def _i3(v):
+    return _lib.I3(*[int(x) for x in v])
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Problem:
+    """C-struct view of a problem description (grid, PML, source, detector, design box, eps).
+
+    ``desc`` is any object with the fields of ``workloads.Problem``.
+    """
+
+    def __init__(self, desc):
+        self.desc = desc
+        self._wave = np.ascontiguousarray(desc.src_wave, np.float32)
+        self._profile = np.ascontiguousarray(desc.src_profile, np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        self.c = FdtdProblem(
+            nx=desc.nx, ny=desc.ny, nz=desc.nz, pml=desc.pml, steps=desc.steps, boundary=desc.boundary,
+            courant=desc.courant, pml_order=desc.pml_order, pml_sigma_scale=desc.pml_sigma_scale,
+            pml_kappa_max=desc.pml_kappa_max, pml_alpha_max=desc.pml_alpha_max, src_comp=desc.src_comp,
+            src_lo=_i3(desc.src_lo), src_hi=_i3(desc.src_hi),
+            src_wave=self._wave.ctypes.data_as(fp), src_profile=self._profile.ctypes.data_as(fp),
+            det_lo=_i3(desc.det_lo), det_hi=_i3(desc.det_hi), des_lo=_i3(desc.des_lo), des_hi=_i3(desc.des_hi))
+
+    @property
+    def shape(self):
+        return (self.desc.nz, self.desc.ny, self.desc.nx)
+
+    @property
+    def design_shape(self):
+        lo, hi = self.desc.des_lo, self.desc.des_hi
+        return (hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0])
+
+    def design_slices(self):
+        lo, hi = self.desc.des_lo, self.desc.des_hi
+        return (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+
+
+def store_config(problem: Problem, dtype: str = "fp32", k: int = 1) -> FdtdStoreInfo:
+    lib = load()
+    cfg = FdtdStoreCfg(STORE_DTYPES[dtype], int(k))
+    info = FdtdStoreInfo()
+    check(lib.store_config(ctypes.byref(problem.c), ctypes.byref(cfg), ctypes.byref(info)))
+    return info
+
+
+@dataclass
+class Buffers:
+    fields: torch.Tensor
+    psi: torch.Tensor
+    store: torch.Tensor
+    workspace: torch.Tensor
+    loss: torch.Tensor
+    series: Optional[torch.Tensor]
+    adj_fields: Optional[torch.Tensor] = None
+    adj_psi: Optional[torch.Tensor] = None
+    grad: Optional[torch.Tensor] = None
+
+
+def _bytes(n, device):
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+class Gradient:
+    """One problem + recorder configuration with its device buffers.
+
+    forward(eps) records and returns the loss; backward() runs the time-reversed
+    pass and returns dL/deps on the design box (float64, [z][y][x]).
+    """
+
+    def __init__(self, problem, dtype: str = "fp32", k: int = 1, device="cuda", series: bool = False,
+                 with_backward: bool = True):
+        self.problem = problem if isinstance(problem, Problem) else Problem(problem)
+        self.dtype = dtype
+        self.k = int(k)
+        self.device = torch.device(device)
+        self.cfg = FdtdStoreCfg(STORE_DTYPES[dtype], self.k)
+        self.info = store_config(self.problem, dtype, k)
+        i = self.info
+        dev = self.device
+        n = int(i.cells)
+        self.buf = Buffers(
+            fields=torch.empty(6 * n, dtype=torch.float32, device=dev),
+            psi=_bytes(i.psi_bytes, dev),
+            store=_bytes(i.store_bytes, dev),
+            workspace=_bytes(i.workspace_bytes, dev),
+            loss=torch.zeros((), dtype=torch.float64, device=dev),
+            series=torch.zeros(self.problem.desc.steps, dtype=torch.float64, device=dev) if series else None)
+        if with_backward:
+            self.buf.adj_fields = torch.empty(6 * n, dtype=torch.float32, device=dev)
+            self.buf.adj_psi = _bytes(i.adj_psi_bytes, dev)
+            self.buf.grad = torch.empty(self.problem.design_shape, dtype=torch.float64, device=dev)
+        self.record = FdtdRecord()
+        self.eps = None
+
+    @property
+    def storage_bytes(self) -> int:
+        return int(self.info.payload_bytes)
+
+    def forward(self, eps: torch.Tensor) -> torch.Tensor:
+        """eps: float32 [nz, ny, nx] on the device.  Returns the loss (0-d float64 tensor)."""
+        assert eps.dtype == torch.float32 and eps.is_contiguous() and eps.device.type == "cuda"
+        assert tuple(eps.shape) == self.problem.shape
+        self.eps = eps
+        b = self.buf
+        check(load().fdtd_forward(
+            ctypes.byref(self.problem.c), ctypes.byref(self.cfg), eps.data_ptr(), b.fields.data_ptr(),
+            b.psi.data_ptr(), b.store.data_ptr(), b.workspace.data_ptr(), b.loss.data_ptr(),
+            b.series.data_ptr() if b.series is not None else None, ctypes.byref(self.record),
+            _stream_handle(self.device)))
+        return b.loss
+
+    def backward(self, grad_scale: Optional[torch.Tensor] = None) -> torch.Tensor:
+        b = self.buf
+        if b.grad is None:
+            raise RuntimeError("constructed without backward buffers")
+        check(load().fdtd_backward(
+            ctypes.byref(self.problem.c), ctypes.byref(self.cfg), self.eps.data_ptr(), b.fields.data_ptr(),
+            b.store.data_ptr(), b.workspace.data_ptr(), b.adj_fields.data_ptr(), b.adj_psi.data_ptr(),
+            grad_scale.data_ptr() if grad_scale is not None else None, b.grad.data_ptr(),
+            ctypes.byref(self.record), _stream_handle(self.device)))
+        return b.grad
+
+    def fields(self):
+        """(E, H) views of the field buffer, each [3, nz, ny, nx]."""
+        f = self.buf.fields.view(6, *self.problem.shape)
+        return f[:3], f[3:]
+
+
+class FDTDGrad(torch.autograd.Function):
+    """loss = FDTDGrad.apply(eps_design, grad_obj, eps_background).
+
+    eps_design: float32 design-box tensor [dz, dy, dx]; eps_background: float32
+    full map [nz, ny, nx] (its design box is overwritten by eps_design).
+    The backward runs the library's time-reversed pass; calling backward a
+    second time on the same forward raises (the fields were reversed).
+    """
+
+    @staticmethod
+    def forward(ctx, eps_design, grad_obj: Gradient, eps_background):
+        eps = eps_background.detach().to(torch.float32).clone().contiguous()
+        eps[grad_obj.problem.design_slices()] = eps_design.detach().to(torch.float32)
+        loss = grad_obj.forward(eps).clone()
+        ctx.grad_obj = grad_obj
+        ctx.in_dtype = eps_design.dtype
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        g = ctx.grad_obj.backward(grad_scale=grad_loss.detach().to(torch.float64).reshape(()).contiguous())
+        return g.to(ctx.in_dtype), None, None
+
+
+def codec_roundtrip(values: torch.Tensor, dtype: str, n_blocks: int):
+    """Encode/decode float32 blocks with the recorder's codec.  Returns (codes, scales, decoded)."""
+    assert values.dtype == torch.float32 and values.is_cuda and values.is_contiguous()
+    block_len = values.numel() // n_blocks
+    assert block_len * n_blocks == values.numel()
+    nbytes = STORAGE_BITS[dtype] // 8
+    code_dtype = {4: torch.int32, 2: torch.int16, 1: torch.uint8}[nbytes]
+    codes = torch.empty(values.numel(), dtype=code_dtype, device=values.device)
+    scales = torch.empty(max(n_blocks, 1), dtype=torch.float32, device=values.device)
+    decoded = torch.empty_like(values)
+    check(load().fdtd_codec_roundtrip(STORE_DTYPES[dtype], values.data_ptr(), n_blocks, block_len,
+                                      codes.data_ptr(), scales.data_ptr(), decoded.data_ptr(),
+                                      _stream_handle(values.device)))
+    return codes, scales[:n_blocks], decoded
+
+
+def timing_enable(on: bool = True):
+    check(load().fdtd_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """{kernel name: (launches, total_ms)} for the launches since timing_enable(True)."""
+    arr = (_lib.FdtdKernelTime * 16)()
+    n = check(load().fdtd_timing_read(arr, 16))
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n)}

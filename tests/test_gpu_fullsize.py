@@ -1,0 +1,96 @@
+"""Checks at the benchmark's full size, in the launch configuration bench.py times (needs an MI355X).
+
+The FP64 oracle would need tens of minutes for one 128^3 x 1000-step gradient,
+so at full size the checks use properties that hold at any size:
+  * the gradient is the derivative of the loss: a directional central
+    difference of the GPU loss along a random design perturbation matches
+    <grad, direction> (the sum over 32768 cells averages FP32 noise away);
+  * time reversal returns the interior to the initial (zero) state;
+  * repeat runs are bitwise identical;
+  * the storage accounting of the compressed recorder (Fig. 3 caption).
+Oracle parity at every tile and ragged-tail shape is covered on smaller grids
+in test_gpu_parity.py.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+import paper_2603_24027_amd as pk
+from oracle import metrics
+
+from gpu_helpers import gpu_run, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _loss(gobj, prob, design):
+    eps = prob.eps.copy()
+    eps[prob.design_slices()] = design.astype(np.float32)
+    t = torch.from_numpy(eps).cuda()
+    return float(gobj.forward(t).item())
+
+
+def test_c2_fp32_gradient_is_derivative_of_loss():
+    require_gpu()
+    prob = w.c2()
+    say("c2 full size: fp32 k=1 gradient, directional derivative, reversal, determinism")
+    out = gpu_run(prob, "fp32", 1, keep_fields=False)
+    g = out["grad"]
+    assert np.all(np.isfinite(g)) and np.linalg.norm(g) > 0
+    # reversal: the interior is back at the zero initial state
+    gobj = out["obj"]
+    E, H = gobj.fields()
+    P = prob.pml
+    I = (slice(None), slice(P, prob.nz - P), slice(P, prob.ny - P), slice(P, prob.nx - P))
+    resid = float(max(E[I].abs().max().item(), H[I].abs().max().item()))
+    peak_run = gpu_run(w.c2(steps=130), "fp32", 1, backward=False)
+    peak = float(max(np.abs(peak_run["E"]).max(), np.abs(peak_run["H"]).max()))
+    say("  reversal residual %.3e of peak %.3e" % (resid, peak))
+    assert resid <= 1e-3 * peak
+    # directional derivative with the GPU forward
+    rng = np.random.default_rng(7)
+    d = rng.standard_normal(prob.design_shape)
+    base = prob.design_eps().astype(np.float64)
+    h = 2e-3
+    fwd = pk.Gradient(prob, "fp32", 1, with_backward=False)
+    lp = _loss(fwd, prob, base + h * d)
+    lm = _loss(fwd, prob, base - h * d)
+    fd = (lp - lm) / (2 * h)
+    ad = float(np.sum(g * d))
+    say("  directional: adjoint %.6e  central difference %.6e" % (ad, fd))
+    assert abs(fd - ad) <= 5e-3 * abs(ad)
+    # determinism
+    again = gpu_run(prob, "fp32", 1, keep_fields=False)
+    assert again["loss"] == out["loss"] and np.array_equal(again["grad"], g)
+
+
+def test_c2_compressed_storage_and_agreement():
+    require_gpu()
+    prob = w.c2()
+    ref = gpu_run(prob, "fp32", 1, keep_fields=False)
+    for dtype, k in [("bf16", 4), ("fp8_e4m3_scaled", 16)]:
+        out = gpu_run(prob, dtype, k, keep_fields=False)
+        ratio = ref["info"].payload_bytes / out["info"].payload_bytes
+        cos = metrics.cosine_similarity(out["grad"], ref["grad"])
+        say("  c2 %s k=%d: storage ratio %.2f, cosine vs fp32 k=1 %.6f, rel-L2 %.3e"
+            % (dtype, k, ratio, cos, metrics.rel_l2(out["grad"], ref["grad"])))
+        assert ratio == pytest.approx(32 / pk.STORAGE_BITS[dtype] * k * (1000 / 16) / np.ceil(1000 / 16)
+                                      if k == 16 else 32 / pk.STORAGE_BITS[dtype] * k, rel=1e-12)
+        assert out["loss"] == pytest.approx(ref["loss"], rel=1e-12)   # the forward does not depend on storage
+        assert np.all(np.isfinite(out["grad"]))
+        assert cos > 0.5
+
+
+def test_paper_regime_fp8_k16_keeps_gradient_direction():
+    """At ~136 steps per period (the paper's Section 2 example), FP8 with k = 16 (64x)
+    keeps the gradient direction of full FP32 storage (Section 3)."""
+    require_gpu()
+    prob = w.c3p()
+    say("c3p (lambda 77.5 cells): fp8 k=16 vs fp32 k=1")
+    ref = gpu_run(prob, "fp32", 1, keep_fields=False)
+    out = gpu_run(prob, "fp8_e4m3_scaled", 16, keep_fields=False)
+    cos = metrics.cosine_similarity(out["grad"], ref["grad"])
+    say("  cosine %.6f rel-L2 %.3e" % (cos, metrics.rel_l2(out["grad"], ref["grad"])))
+    assert cos >= 0.99

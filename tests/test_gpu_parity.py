@@ -1,0 +1,207 @@
+"""HIP path vs FP64 oracle on the same seeded inputs (needs an MI355X).
+
+Tolerances:
+  * fields and loss, FP32 storage k = 1: relative L2 <= 1e-5 (all six components,
+    final state), per-step loss terms <= 1e-5 relative;
+  * gradient, FP32 k = 1: relative L2 <= 1e-4 against the oracle's FP64 gradient
+    (FP32 round-off accumulated over the forward and the reversed sweep);
+  * compressed storage: against the oracle running the same codec and
+    interpolation, cosine >= 0.9999 and relative L2 <= 1e-2 (codes may differ
+    where the FP32 and FP64 recorded values straddle a rounding boundary);
+  * the codec on its own: bit-exact codes, scales and decoded values.
+"""
+
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+import paper_2603_24027_amd as pk
+from oracle import adjoint, codec, metrics, yee
+
+from gpu_helpers import gpu_run, rel, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+ORACLE_MODE = {"fp32": "fp32", "fp16": "fp16", "bf16": "bf16", "fp8_e4m3_scaled": "fp8_e4m3fn_scaled"}
+
+
+def _periodic_problem():
+    n = (24, 20, 16)
+    p = w.dipole_problem("periodic", n, 0, 80, (12, 10, 8), 10.0, (8, 6, 5), (14, 12, 9), (2, 2, 12), (22, 18, 13))
+    return replace(p, boundary=1, name="periodic_24x20x16")
+
+
+CASES = {
+    "tiny": lambda: w.tiny(),
+    "c1": lambda: w.c1(),
+    "ragged": lambda: w.ragged(),
+    "kappa": lambda: replace(w.tiny(n=(20, 18, 16), pml=4, steps=70), pml_kappa_max=3.0, pml_alpha_max=0.15),
+    "periodic": _periodic_problem,
+    "nopml_zero_boundary": lambda: replace(w.tiny(n=(14, 13, 12), steps=50), pml=0),
+}
+
+
+# --------------------------------------------------------------------------- codec
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp16", "bf16", "fp8_e4m3_scaled"])
+def test_codec_bit_exact(dtype):
+    require_gpu()
+    say("codec", dtype)
+    rng = np.random.default_rng(42)
+    blocks = []
+    for b, scale in enumerate([1e-30, 1e-8, 3e-5, 1e-3, 0.02, 1.0, 7.5, 300.0, 1e5, 0.0, 1e-40, 2.0]):
+        x = rng.standard_normal(4099) * scale
+        x[:8] = [0.0, -0.0, scale, -scale, scale * 0.5, 1e-45, -1e-41, scale * (1 + 2 ** -12)]
+        blocks.append(x.astype(np.float32))
+    vals = np.stack(blocks)
+    vals[9] = 0.0                                   # an all-zero block
+    if dtype in ("fp16",):
+        vals = np.clip(vals, -60000, 60000).astype(np.float32)
+    t = torch.from_numpy(vals.ravel().copy()).cuda()
+    codes, scales, dec = pk.codec_roundtrip(t, dtype, vals.shape[0])
+    torch.cuda.synchronize()
+    codes = codes.cpu().numpy()
+    dec = dec.cpu().numpy().reshape(vals.shape)
+    mode = ORACLE_MODE[dtype]
+    for b in range(vals.shape[0]):
+        ref_codes, ref_s = codec.encode_block(vals[b], mode)
+        ref_dec = codec.decode_block(ref_codes, ref_s, mode).astype(np.float32)
+        got = codes.reshape(vals.shape)[b]
+        if dtype == "fp32":
+            assert np.array_equal(got.view(np.float32), ref_codes.astype(np.float32))
+        else:
+            mask = (1 << (8 * got.itemsize)) - 1
+            assert np.array_equal(got.astype(np.int64) & mask, ref_codes), (dtype, b)
+        if dtype == "fp8_e4m3_scaled":
+            assert float(scales[b].item()) == ref_s, (b, float(scales[b].item()), ref_s)
+        assert np.array_equal(dec[b].view(np.uint32), ref_dec.view(np.uint32)), (dtype, b)
+
+
+# --------------------------------------------------------------------------- forward
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_forward_fields_and_loss(case):
+    require_gpu()
+    prob = CASES[case]()
+    say("forward", case, prob.shape, prob.steps)
+    out = gpu_run(prob, series=True, backward=False)
+    s = yee.Solver(prob, match_fp32=True)
+    st, losses, _ = yee.run_forward(s)
+    assert rel(out["E"], st.E) <= 1e-5
+    assert rel(out["H"], st.H) <= 1e-5
+    assert abs(out["loss"] - losses.sum()) <= 1e-5 * abs(losses.sum())
+    big = losses > 1e-6 * losses.max()
+    assert np.max(np.abs(out["series"][big] - losses[big]) / losses[big]) <= 1e-4
+    assert abs(out["series"].sum() - out["loss"]) <= 1e-12 * out["loss"]
+
+
+@pytest.mark.parametrize("frac", [4, 2])
+def test_forward_fields_at_partial_horizon(frac):
+    require_gpu()
+    prob = w.c1(steps=200 // frac)
+    say("forward c1 steps", prob.steps)
+    out = gpu_run(prob, backward=False)
+    st, _, _ = yee.run_forward(yee.Solver(prob, match_fp32=True))
+    assert rel(out["E"], st.E) <= 1e-5 and rel(out["H"], st.H) <= 1e-5
+
+
+# --------------------------------------------------------------------------- gradient
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_gradient_fp32_full_storage(case):
+    require_gpu()
+    prob = CASES[case]()
+    say("gradient fp32 k=1", case)
+    out = gpu_run(prob)
+    L, g = adjoint.grad_time_reversal(prob, "fp64", 1, match_fp32=True)
+    assert abs(out["loss"] - L) <= 1e-5 * abs(L)
+    r = rel(out["grad"], g)
+    cos = metrics.cosine_similarity(out["grad"], g)
+    say("  rel-L2 %.3e cosine %.12f" % (r, cos))
+    assert r <= 1e-4 and cos >= 1 - 1e-8
+
+
+def test_gradient_against_finite_differences():
+    require_gpu()
+    prob = w.tiny()
+    say("gradient vs FD, tiny, all design cells")
+    out = gpu_run(prob)
+    fd = adjoint.grad_finite_difference(prob, np.arange(out["grad"].size), h=1e-4)
+    g = out["grad"].ravel()
+    assert np.all(np.abs(g - fd) <= 1e-4 * np.max(np.abs(fd)) + 1e-4 * np.abs(fd))
+    prob = w.c1()
+    cells = w.fd_cells(prob, 3, seed=0)
+    say("gradient vs FD, c1, cells", cells)
+    out = gpu_run(prob)
+    fd = adjoint.grad_finite_difference(prob, cells, h=1e-4)
+    g = out["grad"].ravel()[cells]
+    scale = np.max(np.abs(out["grad"]))
+    assert np.all(np.abs(g - fd) <= 1e-3 * scale + 1e-3 * np.abs(fd)), (g, fd)
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "fp16", "bf16", "fp8_e4m3_scaled"])
+@pytest.mark.parametrize("k", [1, 3, 16])
+def test_gradient_compressed_against_oracle_compressed(dtype, k):
+    require_gpu()
+    prob = w.c1()
+    say("gradient", dtype, "k", k, "c1")
+    out = gpu_run(prob, dtype, k)
+    _, g = adjoint.grad_time_reversal(prob, ORACLE_MODE[dtype], k, match_fp32=True)
+    r = rel(out["grad"], g)
+    cos = metrics.cosine_similarity(out["grad"], g)
+    say("  vs oracle same codec: rel-L2 %.3e cosine %.9f" % (r, cos))
+    assert cos >= 0.9999 and r <= 1e-2
+    if dtype in ("fp32", "fp16", "bf16") and k in (1, 3):
+        assert r <= 1e-3
+
+
+def test_gradient_ragged_compressed_k_not_dividing_T():
+    require_gpu()
+    prob = w.ragged(steps=37)
+    say("gradient ragged fp8 k=5 (5 does not divide 37)")
+    out = gpu_run(prob, "fp8_e4m3_scaled", 5)
+    _, g = adjoint.grad_time_reversal(prob, "fp8_e4m3fn_scaled", 5, match_fp32=True)
+    assert metrics.cosine_similarity(out["grad"], g) >= 0.9999
+
+
+def test_single_step_and_k_beyond_T():
+    require_gpu()
+    for steps, k in [(1, 1), (6, 10)]:
+        prob = w.tiny(steps=steps)
+        say("gradient tiny steps", steps, "k", k)
+        out = gpu_run(prob, "fp16", k)
+        L, g = adjoint.grad_time_reversal(prob, "fp16", k, match_fp32=True)
+        assert abs(out["loss"] - L) <= 1e-5 * abs(L) + 1e-30
+        if np.linalg.norm(g) > 0:
+            assert metrics.cosine_similarity(out["grad"], g) >= 0.9999
+
+
+# --------------------------------------------------------------------------- binding
+
+def test_autograd_function_and_double_backward():
+    require_gpu()
+    prob = w.tiny()
+    say("autograd tiny")
+    gobj = pk.Gradient(prob, "fp32", 1)
+    bg = torch.from_numpy(prob.eps).cuda()
+    design = torch.from_numpy(prob.design_eps()).cuda().requires_grad_(True)
+    loss = pk.FDTDGrad.apply(design, gobj, bg)
+    (3.0 * loss).backward()
+    _, g = adjoint.grad_time_reversal(prob, "fp64", 1, match_fp32=True)
+    assert rel(design.grad.double().cpu().numpy(), 3.0 * g) <= 1e-4
+    with pytest.raises(pk.FdtdError) as e:
+        gobj.backward()
+    assert e.value.code == -5
+
+
+def test_deterministic_repeat():
+    require_gpu()
+    prob = w.c1()
+    say("determinism c1 fp8 k=4")
+    a = gpu_run(prob, "fp8_e4m3_scaled", 4)
+    b = gpu_run(prob, "fp8_e4m3_scaled", 4)
+    assert a["loss"] == b["loss"]
+    assert np.array_equal(a["grad"], b["grad"])
