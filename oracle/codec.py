@@ -19,6 +19,12 @@ Storage modes used by the gradient oracle:
                          s = 2^e, e the smallest integer with 448 * 2^e >= max|x|
                          (clamped to the normal float32 exponent range), codes
                          q = e4m3fn(x / s); decode float32(value(q) * s)
+    fp8_e4m3b11fnuz, fp8_e5m2fnuz, fp8_e4m3fnuz, fp8_e4m3, fp8_e3m4, fp8_e4m3fn
+                         the unscaled 8-bit types of Section 3 (Fig. 3): round to
+                         float32, then straight to the format (no scale).  Names:
+                         eXmY = exponent / mantissa bits; "fn" finite with NaN,
+                         "fnuz" finite, NaN, unsigned zero; b11 = exponent bias
+                         11 (the others use 2^(X-1) - 1, fnuz types one more).
 """
 
 from __future__ import annotations
@@ -35,7 +41,8 @@ class FloatFormat:
     exp_bits: int
     man_bits: int
     bias: int
-    kind: str        # "ieee": top exponent = inf/nan; "fn": only S.1111.111 is NaN (no inf)
+    kind: str        # "ieee": top exponent = inf/nan; "fn": only S.1111.111 is NaN (no inf);
+                     # "fnuz": only 1.0000.000 (negative zero) is NaN, no inf, no negative zero
 
     @property
     def bits(self) -> int:
@@ -45,8 +52,16 @@ class FloatFormat:
 FP16 = FloatFormat("fp16", 5, 10, 15, "ieee")
 BF16 = FloatFormat("bf16", 8, 7, 127, "ieee")
 FP8_E4M3FN = FloatFormat("fp8_e4m3fn", 4, 3, 7, "fn")
+# the unscaled 8-bit family compared in Section 3 / Fig. 3
+FP8_E4M3B11FNUZ = FloatFormat("fp8_e4m3b11fnuz", 4, 3, 11, "fnuz")
+FP8_E5M2FNUZ = FloatFormat("fp8_e5m2fnuz", 5, 2, 16, "fnuz")
+FP8_E4M3FNUZ = FloatFormat("fp8_e4m3fnuz", 4, 3, 8, "fnuz")
+FP8_E4M3 = FloatFormat("fp8_e4m3", 4, 3, 7, "ieee")
+FP8_E3M4 = FloatFormat("fp8_e3m4", 3, 4, 3, "ieee")
+UNSCALED_FP8 = {f.name: f for f in (FP8_E4M3B11FNUZ, FP8_E5M2FNUZ, FP8_E4M3FNUZ, FP8_E4M3, FP8_E3M4, FP8_E4M3FN)}
 
-STORAGE_BITS = {"fp64": 64, "fp32": 32, "fp16": 16, "bf16": 16, "fp8_e4m3fn_scaled": 8}
+STORAGE_BITS = {"fp64": 64, "fp32": 32, "fp16": 16, "bf16": 16, "fp8_e4m3fn_scaled": 8,
+                **{name: 8 for name in UNSCALED_FP8}}
 FP8_MAX = 448.0
 
 
@@ -60,6 +75,8 @@ def code_value(fmt: FloatFormat, code: int) -> float:
     if fmt.kind == "ieee" and e == e_max:
         return sign * math.inf if m == 0 else math.nan
     if fmt.kind == "fn" and e == e_max and m == m_mask:
+        return math.nan
+    if fmt.kind == "fnuz" and code == 1 << (fmt.exp_bits + fmt.man_bits):
         return math.nan
     if e == 0:
         return sign * (m / (1 << fmt.man_bits)) * 2.0 ** (1 - fmt.bias)
@@ -111,9 +128,13 @@ def encode(x, fmt: FloatFormat) -> np.ndarray:
     pick_hi = (d_hi < d_lo) | ((d_hi == d_lo) & (ext_codes[hi] % 2 == 0))
     out = np.where(pick_hi, ext_codes[hi], ext_codes[lo])
     out = np.where(a >= ov_val, ov_code, out)                # at or past the overflow value
-    out = np.where(np.signbit(x), out | sign_bit, out)
-    nan_code = (1 << (fmt.exp_bits + fmt.man_bits)) - 1 if fmt.kind == "fn" else \
-        (((1 << fmt.exp_bits) - 1) << fmt.man_bits) | (1 << (fmt.man_bits - 1))
+    if fmt.kind == "fnuz":                                    # no negative zero; the sign bit alone is NaN
+        out = np.where(np.signbit(x) & (out != 0), out | sign_bit, out)
+        nan_code = sign_bit
+    else:
+        out = np.where(np.signbit(x), out | sign_bit, out)
+        nan_code = (1 << (fmt.exp_bits + fmt.man_bits)) - 1 if fmt.kind == "fn" else \
+            (((1 << fmt.exp_bits) - 1) << fmt.man_bits) | (1 << (fmt.man_bits - 1))
     out = np.where(np.isnan(x), nan_code, out)
     return out.astype(np.int64)
 
@@ -158,6 +179,8 @@ def encode_block(x32: np.ndarray, mode: str):
         m = float(np.max(np.abs(x32))) if x32.size else 0.0
         s = 2.0 ** fp8_scale_exponent(m)
         return encode(x32.astype(np.float64) / s, FP8_E4M3FN), s
+    if mode in UNSCALED_FP8:
+        return encode(x32, UNSCALED_FP8[mode]), 1.0
     raise ValueError(mode)
 
 
@@ -171,6 +194,8 @@ def decode_block(codes, scale: float, mode: str) -> np.ndarray:
         return decode(codes, BF16).astype(np.float32).astype(np.float64)
     if mode == "fp8_e4m3fn_scaled":
         return (decode(codes, FP8_E4M3FN) * scale).astype(np.float32).astype(np.float64)
+    if mode in UNSCALED_FP8:
+        return decode(codes, UNSCALED_FP8[mode]).astype(np.float32).astype(np.float64)
     raise ValueError(mode)
 
 

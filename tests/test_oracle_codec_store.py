@@ -182,3 +182,66 @@ def test_cosine_similarity_eq2():
     assert metrics.cosine_similarity([1, 0], [0, 2]) == 0.0
     assert metrics.cosine_similarity([1, 1], [1, 0]) == pytest.approx(1 / math.sqrt(2), rel=1e-15)
     assert metrics.rel_l2([1.1, 2.0], [1.0, 2.0]) == pytest.approx(0.1 / math.sqrt(5), rel=1e-12)
+
+
+# -- the unscaled 8-bit family of Section 3 (Fig. 3) ----------------------------
+
+_TORCH_FNUZ = {"fp8_e4m3fnuz": torch.float8_e4m3fnuz, "fp8_e5m2fnuz": torch.float8_e5m2fnuz}
+
+
+def _lib_codes(x32, dt):
+    return torch.from_numpy(np.ascontiguousarray(x32, np.float32)).to(dt).view(torch.uint8).numpy().astype(np.int64)
+
+
+@pytest.mark.parametrize("name", ["fp8_e4m3fnuz", "fp8_e5m2fnuz"])
+def test_fnuz_encode_decode_match_library(name):
+    fmt = codec.UNSCALED_FP8[name]
+    rng = np.random.default_rng(3)
+    x = _probe_values(fmt, rng)
+    assert np.array_equal(codec.encode(x, fmt), _lib_codes(x, _TORCH_FNUZ[name]))
+    # overflow and the sign of zero
+    edge = np.array([1e9, -1e9, -0.0, -1e-30, np.nan], np.float32)
+    assert np.array_equal(codec.encode(edge, fmt), _lib_codes(edge, _TORCH_FNUZ[name]))
+    codes = np.arange(256)
+    ref = torch.tensor(codes, dtype=torch.uint8).view(_TORCH_FNUZ[name]).to(torch.float64).numpy()
+    mine = codec.decode(codes, fmt)
+    assert np.array_equal(np.isnan(mine), np.isnan(ref))
+    fin = ~np.isnan(ref)
+    assert np.array_equal(mine[fin], ref[fin])
+
+
+def test_e4m3b11fnuz_is_e4m3fnuz_scaled_by_eight():
+    """Bias 11 vs bias 8 with identical fields: code(x) in b11 == code(8 x) in fnuz, value / 8."""
+    fmt = codec.FP8_E4M3B11FNUZ
+    rng = np.random.default_rng(4)
+    x = _probe_values(fmt, rng)
+    assert np.array_equal(codec.encode(x, fmt), _lib_codes(8.0 * x.astype(np.float64), torch.float8_e4m3fnuz))
+    codes = np.arange(256)
+    ref = torch.tensor(codes, dtype=torch.uint8).view(torch.float8_e4m3fnuz).to(torch.float64).numpy() / 8.0
+    mine = codec.decode(codes, fmt)
+    fin = ~np.isnan(ref)
+    assert np.array_equal(mine[fin], ref[fin]) and np.isnan(mine[~fin]).all()
+    assert np.max(mine[fin]) == 30.0 and np.min(mine[fin & (mine > 0)]) == 2.0 ** -13
+
+
+def test_ieee_e4m3_agrees_with_e4m3fn_below_its_overflow():
+    """IEEE-style e4m3 shares bias and fields with e4m3fn for exponent fields below 15 (max 240)."""
+    fmt = codec.FP8_E4M3
+    rng = np.random.default_rng(5)
+    x = _probe_values(fmt, rng)
+    x = x[np.abs(x.astype(np.float64)) < 248.0]
+    assert np.array_equal(codec.encode(x, fmt), _lib_codes(x, torch.float8_e4m3fn))
+    assert codec.decode(codec.encode(np.array([248.0, -1e3]), fmt), fmt).tolist() == [np.inf, -np.inf]
+    assert codec.decode(np.array([0x78, 0x7f]), fmt)[0] == np.inf and np.isnan(codec.decode([0x7f], fmt)[0])
+
+
+def test_e3m4_definition_constants():
+    """No library cast exists for e3m4; its table comes from the generic field decoder pinned
+    above on six formats.  Check the constants its definition fixes (bias 3, IEEE specials)."""
+    fmt = codec.FP8_E3M4
+    vals = codec.decode(np.arange(128), fmt)
+    fin = vals[np.isfinite(vals)]
+    assert fin.max() == 15.5 and fin[fin > 0].min() == 2.0 ** -6
+    assert codec.decode([0x10], fmt)[0] == 0.25          # smallest normal 2^(1-3)
+    assert codec.decode([0x70], fmt)[0] == np.inf
+    assert codec.encode(np.array([15.75, 15.7]), fmt).tolist() == [0x70, 0x6F]   # tie to even -> inf
