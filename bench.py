@@ -1,0 +1,301 @@
+"""Benchmark of the time-reversible FDTD gradient on one MI355X.
+
+One "step" is one full gradient evaluation: the forward pass over T time
+steps with interface recording, then the time-reversed pass over T steps that
+returns dL/deps.  Throughput is fwd+rev Mcell-steps/s = cells * T / time.
+
+Default workload: 128^3 cells with a 10-cell CPML, 1000 time steps, FP32
+fields, interface fields stored in FP32 at every step, a 32^3 seeded-random
+design block, a dipole source and a 64 x 64 detector plane.  The compressed
+recorder (FP8-E4M3 with per-block scales, k = 16) is timed in the same run.
+
+Prints one JSON line (see the keys below).  Run with --gpus 1 only: this build
+measures one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+rev Mcell-steps/s, boundary-store GB, grad rel-err vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    # name: (preset, preset kwargs, store dtype, k)
+    "c2": ("c2", {}, "fp32", 1),
+    "c4": ("c4", {}, "fp32", 1),
+    "c5": ("c5", {}, "fp32", 1),
+    "c3p": ("c3p", {}, "fp32", 1),
+}
+KERNEL_SOURCES = ["paper_2603_24027_amd/csrc/common.h", "paper_2603_24027_amd/csrc/forward.hip",
+                  "paper_2603_24027_amd/csrc/reverse.hip", "paper_2603_24027_amd/csrc/api.hip"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(prob, design_cells: int):
+    """Minimal HBM bytes per launch of each kernel (each value read once, written once).
+
+    fwd_step and adj_step sweep every cell: 52 B (read the six field components
+    and eps, write the six) plus 32 B per PML slab cell and axis (four auxiliaries
+    read and written).  prim_rev sweeps the interior: 52 B per interior cell plus
+    the FP64 gradient (16 B read-modify-write) and the adjoint E it reads (12 B)
+    per design cell.
+    """
+    P = prob.pml
+    N = prob.nx * prob.ny * prob.nz
+    NI = (prob.nx - 2 * P) * (prob.ny - 2 * P) * (prob.nz - 2 * P)
+    NP = N - NI
+    S = 2 * P * (prob.ny * prob.nz + prob.nx * prob.nz + prob.nx * prob.ny)
+    return {
+        "fwd_step": 52 * N + 32 * S,
+        "prim_rev": 52 * NI + 28 * design_cells,
+        "adj_step": 52 * N + 32 * S,
+        # single-sweep lower bound of one time step, fwd + rev (52 B forward; 100 B interior /
+        # 52 B PML reverse; PML auxiliaries; FP64 gradient)
+        "step_min": 52 * N + 100 * NI + 52 * NP + 64 * S + 16 * design_cells,
+    }
+
+
+def oracle_baseline(prob_fn, sample_steps: int):
+    """Time the FP64 oracle (as it stands) on the first steps of the workload's grid."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle import adjoint
+    prob = prob_fn(steps=sample_steps)
+    t0 = time.perf_counter()
+    adjoint.grad_time_reversal(prob, "fp32", 1, match_fp32=True)
+    dt = time.perf_counter() - t0
+    return prob.cells * sample_steps / dt / 1e6, dt, prob
+
+
+def oracle_grad_error(dtype_pairs):
+    """Gradient relative L2 error of the GPU path vs the FP64 oracle on the 32^3, 200-step case."""
+    import torch
+    import workloads as w
+    import paper_2603_24027_amd as pk
+    from oracle import adjoint, metrics
+    prob = w.c1()
+    _, g_exact = adjoint.grad_time_reversal(prob, "fp64", 1)
+    res = {}
+    for dtype, k in dtype_pairs:
+        gobj = pk.Gradient(prob, dtype, k)
+        gobj.forward(torch.from_numpy(prob.eps).cuda())
+        g = gobj.backward().cpu().numpy()
+        res["%s_k%d" % (dtype, k)] = {"rel_l2": metrics.rel_l2(g, g_exact),
+                                      "cosine": metrics.cosine_similarity(g, g_exact)}
+    return res
+
+
+SWEEP_TYPES = ["fp32", "fp16", "bf16", "fp8_e4m3_scaled", "fp8_e4m3b11fnuz", "fp8_e5m2fnuz", "fp8_e4m3fnuz",
+               "fp8_e4m3", "fp8_e3m4", "fp8_e4m3fn"]
+SWEEP_K = [1, 2, 4, 8, 16, 32]
+
+
+def run_sweep(args, w, pk, torch, dev):
+    """Mean cosine similarity (Eq. 2) of compressed-storage gradients against FP32 storage at
+    every step, over seeded random designs, for each storage type and k; one JSON line each."""
+    from oracle import metrics   # metric only; every gradient comes from the HIP path
+    preset, kw, _, _ = WORKLOADS[args.workload]
+    probs = [w.make(preset, seed=s, **kw) for s in range(args.sweep_seeds)]
+    refs = []
+    for p in probs:
+        g = pk.Gradient(p, "fp32", 1, device=dev)
+        g.forward(torch.from_numpy(p.eps).to(dev))
+        refs.append(g.backward().cpu().numpy().copy())
+    full = pk.store_config(pk.Problem(probs[0]), "fp32", 1).payload_bytes
+    for dtype in SWEEP_TYPES:
+        for k in SWEEP_K:
+            cos, rel = [], []
+            t0 = time.perf_counter()
+            for p, ref in zip(probs, refs):
+                g = pk.Gradient(p, dtype, k, device=dev)
+                g.forward(torch.from_numpy(p.eps).to(dev))
+                gr = g.backward().cpu().numpy()
+                finite = bool(np.all(np.isfinite(gr)))
+                cos.append(metrics.cosine_similarity(gr, ref) if finite else float("nan"))
+                rel.append(metrics.rel_l2(gr, ref) if finite else float("nan"))
+            info = pk.store_config(pk.Problem(probs[0]), dtype, k)
+            print(json.dumps({"sweep": probs[0].name, "store_dtype": dtype, "k": k,
+                              "compression": round(full / info.payload_bytes, 3),
+                              "storage_GB": info.payload_bytes / 1e9,
+                              "cosine_mean": float(np.mean(cos)), "cosine_min": float(np.min(cos)),
+                              "rel_l2_mean": float(np.mean(rel)), "seeds": len(probs),
+                              "s_per_gradient": round((time.perf_counter() - t0) / len(probs), 4)}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed gradient evaluations")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compressed", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=60)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (for counter scaling) and exit")
+    ap.add_argument("--sweep", action="store_true",
+                    help="storage type x k sweep of gradient agreement (Fig. 3 analogue) instead of the benchmark")
+    ap.add_argument("--sweep-seeds", type=int, default=3)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU; --gpus %d is not supported by this build "
+              "(the multi-GPU decomposition is a design only)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as w
+    import paper_2603_24027_amd as pk
+
+    pk.load()                      # fails loudly without the HIP library
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 3}))
+        return
+
+    if args.sweep:
+        run_sweep(args, w, pk, torch, dev)
+        return
+
+    preset, kw, dtype, k = WORKLOADS[args.workload]
+    prob_fn = lambda **extra: w.make(preset, **{**kw, **extra})
+    prob = prob_fn()
+    eps = torch.from_numpy(prob.eps).to(dev)
+    T = prob.steps
+    cells = prob.cells
+
+    def timed_run(dtype_, k_, steps, warmup):
+        gobj = pk.Gradient(prob, dtype_, k_, device=dev)
+        for _ in range(warmup):
+            gobj.forward(eps)
+            gobj.backward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            gobj.forward(eps)
+            gobj.backward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0), gobj
+
+    def kernel_times(gobj, steps):
+        """Per-kernel HIP events (start/stop carried by each dispatch) over `steps` gradients."""
+        pk.timing_enable(True)             # one pass to create the event pool
+        gobj.forward(eps)
+        gobj.backward()
+        pk.timing_read()
+        pk.timing_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            gobj.forward(eps)
+            gobj.backward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = pk.timing_read()
+        pk.timing_enable(False)
+        return kt, t1 - t0
+
+    elapsed, gobj = timed_run(dtype, k, args.steps, args.warmup)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = cells * T * args.steps / elapsed / 1e6
+    ktimes, kt_elapsed = kernel_times(gobj, args.steps)
+
+    design_cells = int(np.prod(prob.design_shape))
+    ab = algorithmic_bytes(prob, design_cells)
+    kernels = {}
+    for name in ("fwd_step", "prim_rev", "adj_step"):
+        launches, total_ms = ktimes[name]
+        avg_s = total_ms / launches / 1e3
+        kernels[name] = {"launches": launches, "avg_us": avg_s * 1e6,
+                         "alg_bytes": ab[name], "GBps": ab[name] / avg_s / 1e9}
+    dominant = max(kernels, key=lambda n: kernels[n]["avg_us"] * kernels[n]["launches"])
+    dk = kernels[dominant]
+    traffic = None
+    pmc_path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (dominant, prob.name))
+    if os.path.exists(pmc_path):
+        with open(pmc_path) as f:
+            pmc = json.load(f)
+        if pmc.get("kernel_source_hash") == kernel_source_hash():
+            traffic = pmc.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(dk["GBps"], 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "alg_bytes_per_launch": ab[dominant], "avg_launch_us": round(dk["avg_us"], 2)}
+    step_gbs = ab["step_min"] * T * args.steps / elapsed / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "grid": [prob.nx, prob.ny, prob.nz], "pml": prob.pml,
+                   "time_steps": T, "store_dtype": dtype, "k": k, "design_cells": design_cells,
+                   "wavelength_cells": prob.wavelength},
+        "boundary_store_GB": gobj.info.payload_bytes / 1e9,
+        "roofline": roofline,
+        "whole_step": {"alg_bytes_per_time_step": ab["step_min"], "GBps": round(step_gbs, 1),
+                       "frac_of_hbm_peak": round(step_gbs / HBM_PEAK_GBS, 4),
+                       "note": "single-sweep minimum bytes (fwd 52 B/cell, rev 100 B interior / 52 B PML "
+                               "+ PML auxiliaries) over the measured fwd+rev time"},
+        "kernels": {n: {kk: (round(v, 2) if isinstance(v, float) else v) for kk, v in d.items()}
+                    for n, d in kernels.items()},
+        "kernel_timing_pass_ms_per_step": round(kt_elapsed / args.steps * 1e3, 3),
+        "other_kernels": {n: {"launches": l, "total_ms": round(t, 3)} for n, (l, t) in ktimes.items()
+                          if n not in kernels},
+    }
+
+    if not args.no_compressed:
+        c_el, c_obj = timed_run("fp8_e4m3_scaled", 16, args.steps, args.warmup)
+        out["compressed"] = {"store_dtype": "fp8_e4m3_scaled", "k": 16,
+                             "value": round(cells * T * args.steps / c_el / 1e6, 1),
+                             "ms_per_step": round(c_el / args.steps * 1e3, 3),
+                             "boundary_store_GB": c_obj.info.payload_bytes / 1e9,
+                             "storage_reduction": gobj.info.payload_bytes / c_obj.info.payload_bytes}
+
+    if not args.no_cpu_baseline:
+        mcs, dt_cpu, sprob = oracle_baseline(prob_fn, args.cpu_sample_steps)
+        out["cpu_baseline"] = {"value": round(mcs, 4), "unit": "Mcell-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 NumPy oracle, time-reversal gradient (forward + reverse) of the "
+                                         "same grid truncated to %d time steps: %.1f s on %s"
+                                         % (args.cpu_sample_steps, dt_cpu, platform.processor() or
+                                            platform.machine())}
+        out["grad_rel_err_vs_fp64_oracle"] = {
+            "workload": "c1_32cube (32^3, 8-cell CPML, 200 steps; the oracle-sized case)",
+            **oracle_grad_error([(dtype, k), ("fp8_e4m3_scaled", 16)])}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

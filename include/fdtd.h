@@ -65,6 +65,16 @@ extern "C" {
                                             power-of-two s per (kept step, face, component):
                                             s = 2^e, e the smallest integer such that
                                             448 * 2^e >= max|x|, clamped to [-126, 127]     */
+/* The unscaled 8-bit types compared in Section 3 (Fig. 3): eXmY = exponent and
+ * mantissa bits; "fn" = finite with NaN; "fnuz" = finite, NaN, unsigned zero;
+ * b11 = exponent bias 11.  Values past the largest finite one become inf (IEEE
+ * style) or NaN, as a plain (non-saturating) conversion gives. */
+#define FDTD_STORE_FP8_E4M3B11FNUZ   4   /* bias 11, max 30, smallest subnormal 2^-13      */
+#define FDTD_STORE_FP8_E5M2FNUZ      5   /* bias 16, max 57344                              */
+#define FDTD_STORE_FP8_E4M3FNUZ      6   /* bias 8, max 240                                 */
+#define FDTD_STORE_FP8_E4M3          7   /* IEEE style, bias 7, max 240                     */
+#define FDTD_STORE_FP8_E3M4          8   /* IEEE style, bias 3, max 15.5                    */
+#define FDTD_STORE_FP8_E4M3FN        9   /* OCP E4M3 without a scale, max 448               */
 
 #define FDTD_MAX_PML 64
 
@@ -72,7 +82,7 @@ extern "C" {
  * Problem statement: grid with PML faces, permittivity map, source, detector
  * and Courant number (Section 2 and Eq. 1; PML from Section 1).
  *
- *   nx, ny, nz      full grid in cells, PML included (each >= 1)
+ *   nx, ny, nz      full grid in cells, PML included (each >= 1; 6 * cells < 2^31)
  *   pml             PML thickness P on all six faces (0 <= P <= FDTD_MAX_PML,
  *                   2P < each extent); the interior I is [P, n-P) on each axis
  *   steps           T >= 1 time steps
@@ -126,10 +136,11 @@ typedef struct {
     uint64_t scale_bytes;       /* 12 float scales per kept step (FP8 only)              */
     uint64_t store_bytes;       /* size of the store buffer (payload, padding, scales)   */
     uint64_t fields_bytes;      /* 6 * cells * 4: Ex Ey Ez Hx Hy Hz                      */
-    uint64_t psi_bytes;         /* forward PML auxiliaries                               */
+    uint64_t psi_bytes;         /* forward PML auxiliaries (H side in two copies)        */
     uint64_t adj_psi_bytes;     /* backward PML auxiliaries (two copies, ping-pong)      */
     uint64_t workspace_bytes;   /* coefficient tables, source profile, loss partials,
-                                   recorder staging                                      */
+                                   recorder staging, and two more field buffers (the
+                                   ping-pong partners of fields and adj_fields)          */
     uint64_t design_cells;      /* cells of the design box (length of the gradient)      */
 } fdtd_store_info_t;
 
@@ -209,6 +220,16 @@ typedef struct {
 } fdtd_kernel_time_t;
 
 FDTD_API int fdtd_timing_enable(int32_t enable);
+
+/*
+ * Launch-sequence replay.  By default a forward or backward call whose
+ * problem, store configuration, buffer pointers and device equal those of an
+ * earlier call replays that call's kernel sequence as one HIP graph (captured
+ * once, up to 16 kept) instead of enqueuing T launches from the host; the
+ * kernels and their results are the same.  fdtd_set_graphs(0) enqueues every
+ * launch directly.  Per-kernel timing always enqueues directly.
+ */
+FDTD_API int fdtd_set_graphs(int32_t enable);
 FDTD_API int fdtd_timing_read(fdtd_kernel_time_t* out, int32_t max_kinds);
 
 FDTD_API const char* fdtd_strerror(int code);

@@ -7,4 +7,4 @@ calls into the library fail loudly if it has not been built.
 
 from ._lib import FdtdError, LIB_PATH, load  # noqa: F401
 from .solver import (STORAGE_BITS, STORE_DTYPES, FDTDGrad, Gradient, Problem, codec_roundtrip,  # noqa: F401
-                     store_config, timing_enable, timing_read)
+                     set_graphs, store_config, timing_enable, timing_read)

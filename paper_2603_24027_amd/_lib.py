@@ -21,6 +21,12 @@ STORE_FP32 = 0
 STORE_FP16 = 1
 STORE_BF16 = 2
 STORE_FP8_E4M3_SCALED = 3
+STORE_FP8_E4M3B11FNUZ = 4
+STORE_FP8_E5M2FNUZ = 5
+STORE_FP8_E4M3FNUZ = 6
+STORE_FP8_E4M3 = 7
+STORE_FP8_E3M4 = 8
+STORE_FP8_E4M3FN = 9
 
 I3 = ctypes.c_int32 * 3
 
@@ -65,7 +71,7 @@ class FdtdKernelTime(ctypes.Structure):
 
 
 EXPORTS = ("store_config", "fdtd_forward", "fdtd_backward", "fdtd_codec_roundtrip", "fdtd_timing_enable",
-           "fdtd_timing_read", "fdtd_strerror", "fdtd_last_error")
+           "fdtd_timing_read", "fdtd_set_graphs", "fdtd_strerror", "fdtd_last_error")
 
 _lib = None
 
@@ -92,9 +98,10 @@ def load() -> ctypes.CDLL:
                                   P(FdtdRecord), vp]
     lib.fdtd_codec_roundtrip.argtypes = [ctypes.c_int32, vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp]
     lib.fdtd_timing_enable.argtypes = [ctypes.c_int32]
+    lib.fdtd_set_graphs.argtypes = [ctypes.c_int32]
     lib.fdtd_timing_read.argtypes = [P(FdtdKernelTime), ctypes.c_int32]
     for name in ("store_config", "fdtd_forward", "fdtd_backward", "fdtd_codec_roundtrip",
-                 "fdtd_timing_enable", "fdtd_timing_read"):
+                 "fdtd_timing_enable", "fdtd_timing_read", "fdtd_set_graphs"):
         getattr(lib, name).restype = ctypes.c_int
     lib.fdtd_strerror.argtypes = [ctypes.c_int]
     lib.fdtd_strerror.restype = ctypes.c_char_p

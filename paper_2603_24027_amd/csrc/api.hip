@@ -4,13 +4,15 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/fdtd.h"
-#include "common.h"
+#include "march.h"
 
 using namespace fdtd;
 
@@ -31,6 +33,12 @@ int fail(int code, const char* fmt, ...) {
 
 uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
+// Tuning override for tile sizes (read once per call; defaults otherwise).
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return v && *v ? std::atoi(v) : dflt;
+}
+
 uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
     const unsigned char* c = (const unsigned char*)p;
     for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
@@ -39,8 +47,11 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
 
 struct Plan {
     Grid g;
+    Tiling fwd;            // forward and adjoint sweeps: the whole grid
+    Tiling rev;            // primal reversal: the interior plus its shell
+    int box_o[3], box_n[3];
     fdtd_store_info_t info;
-    uint64_t ws_coef = 0, ws_profile = 0, ws_partials = 0, ws_staging = 0;
+    uint64_t ws_coef = 0, ws_profile = 0, ws_partials = 0, ws_staging = 0, ws_fields = 0;
     uint64_t psi_floats = 0;
     int per_step = 0;
     int64_t src_volume = 0;
@@ -86,8 +97,9 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     if (!p || !cfg) return fail(FDTD_EINVAL, "problem and store config must not be NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(FDTD_EINVAL, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
-    if (p->ny > 4 * 65535 || p->nz > 65535 || (int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 36)
-        return fail(FDTD_EINVAL, "grid too large for this build");
+    // kernels index one field buffer (6 components) with 32-bit offsets
+    if (p->ny > 4 * 65535 || p->nz > 65535 || 6 * (int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
+        return fail(FDTD_EINVAL, "grid too large: 6 * cells must stay below 2^31");
     if (p->steps < 1) return fail(FDTD_EINVAL, "steps must be >= 1 (got %d)", p->steps);
     if (p->pml < 0 || p->pml > FDTD_MAX_PML) return fail(FDTD_EINVAL, "pml must be in [0, %d]", FDTD_MAX_PML);
     const int n[3] = {p->nx, p->ny, p->nz};
@@ -109,7 +121,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
         return fail(FDTD_EREGION, "detector box must be non-empty and inside the interior");
     if (!box_inside_interior(p->des_lo, p->des_hi, n, p->pml))
         return fail(FDTD_EREGION, "design box must be non-empty and inside the interior");
-    if (cfg->dtype < FDTD_STORE_FP32 || cfg->dtype > FDTD_STORE_FP8_E4M3_SCALED)
+    if (cfg->dtype < FDTD_STORE_FP32 || cfg->dtype > FDTD_STORE_FP8_E4M3FN)
         return fail(FDTD_ESTORE, "unknown storage type %d", cfg->dtype);
     if (cfg->k < 1) return fail(FDTD_ESTORE, "subsampling k must be >= 1 (got %d)", cfg->k);
 
@@ -146,7 +158,27 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     g.dbx0 = p->det_lo[0] / BX; g.dnbx = (p->det_hi[0] - 1) / BX - g.dbx0 + 1;
     g.dby0 = p->det_lo[1] / BY; g.dnby = (p->det_hi[1] - 1) / BY - g.dby0 + 1;
     g.dbz0 = p->det_lo[2];      g.dnbz = p->det_hi[2] - p->det_lo[2];
-    pl->per_step = g.dnbx * g.dnby * g.dnbz;
+    Tiling& t = pl->fwd;
+    t.ty = env_int("FDTD_TILE_Y", 8) == 4 ? 4 : 8;
+    t.cz = std::max(1, std::min(env_int("FDTD_TILE_Z", 8), p->nz));
+    t.ntx = (p->nx + TX - 1) / TX;
+    t.nty = (p->ny + t.ty - 1) / t.ty;
+    t.ntz = (p->nz + t.cz - 1) / t.cz;
+    t.count = t.ntx * t.nty * t.ntz;
+    t.dtx0 = p->det_lo[0] / TX; t.dntx = (p->det_hi[0] - 1) / TX - t.dtx0 + 1;
+    t.dty0 = p->det_lo[1] / t.ty; t.dnty = (p->det_hi[1] - 1) / t.ty - t.dty0 + 1;
+    t.dtz0 = p->det_lo[2] / t.cz; t.dntz = (p->det_hi[2] - 1) / t.cz - t.dtz0 + 1;
+    pl->per_step = t.dntx * t.dnty * t.dntz;
+    for (int d = 0; d < 3; ++d) {
+        pl->box_o[d] = P > 0 ? P - 1 : 0;
+        pl->box_n[d] = P > 0 ? n[d] - 2 * P + 2 : n[d];
+    }
+    Tiling& r = pl->rev;
+    r = t;
+    r.ntx = (pl->box_n[0] + TX - 1) / TX;
+    r.nty = (pl->box_n[1] + r.ty - 1) / r.ty;
+    r.ntz = (pl->box_n[2] + r.cz - 1) / r.cz;
+    r.count = r.ntx * r.nty * r.ntz;
     pl->psi_floats = (uint64_t)g.psi_total;
     pl->src_volume = (int64_t)(p->src_hi[0] - p->src_lo[0]) * (p->src_hi[1] - p->src_lo[1]) *
                      (p->src_hi[2] - p->src_lo[2]);
@@ -160,14 +192,16 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     in.scale_bytes = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? slices * 12 * 4 : 0;
     in.store_bytes = std::max<uint64_t>(256, (uint64_t)g.scale_off + align_up(in.scale_bytes, 256));
     in.fields_bytes = 6ull * (uint64_t)N * 4;
-    in.psi_bytes = std::max<uint64_t>(256, pl->psi_floats * 4);
+    in.psi_bytes = std::max<uint64_t>(256, 2 * pl->psi_floats * 4);
     in.adj_psi_bytes = std::max<uint64_t>(512, 2 * pl->psi_floats * 4);
     pl->ws_coef = 0;
     pl->ws_profile = align_up(12ull * P * 4, 256);
     pl->ws_partials = pl->ws_profile + align_up((uint64_t)pl->src_volume * 4, 256);
     pl->ws_staging = pl->ws_partials + align_up((uint64_t)p->steps * pl->per_step * 8, 256);
     const uint64_t staging = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? align_up((uint64_t)vps * 4, 256) : 0;
-    in.workspace_bytes = pl->ws_staging + staging;
+    pl->ws_fields = pl->ws_staging + staging;
+    // second primal and second adjoint field buffers (ping-pong)
+    in.workspace_bytes = pl->ws_fields + 2 * in.fields_bytes;
     in.design_cells = (uint64_t)(p->des_hi[0] - p->des_lo[0]) * (p->des_hi[1] - p->des_lo[1]) *
                       (p->des_hi[2] - p->des_lo[2]);
 
@@ -211,8 +245,8 @@ int check_hip(const char* what) {
 }
 
 // ---- per-kernel timing ------------------------------------------------------
-const char* kKindNames[K_NUM_KINDS] = {"fill", "fwd_h", "fwd_e", "rec_quant", "loss_final",
-                                       "rev_init", "rev_e", "rev_h", "scale_grad", "codec"};
+const char* kKindNames[K_NUM_KINDS] = {"fill", "fwd_step", "rec_quant", "loss_final", "inject_h",
+                                       "prim_rev", "adj_step", "scale_grad", "codec"};
 constexpr size_t kMaxTimedLaunches = 1 << 16;
 
 struct Timing {
@@ -222,6 +256,19 @@ struct Timing {
     std::vector<int> kinds;            // kind of each timed launch
     size_t used = 0;
 } g_timing;
+
+// ---- HIP-graph replay of the time loops ------------------------------------
+// A call whose problem, configuration, buffers and device match an earlier one
+// replays that call's launch sequence as one graph: the T-step loop is
+// captured once (on an internal stream) and then launched on the caller's
+// stream.  Per-kernel timing bypasses graphs.
+struct GraphCache {
+    std::mutex mu;
+    bool enabled = true;
+    std::vector<std::pair<uint64_t, hipGraphExec_t>> entries;   // most recent last
+    hipStream_t capture[64] = {};                                // per device
+} g_graphs;
+constexpr size_t kMaxGraphs = 16;
 
 }  // namespace
 
@@ -243,6 +290,64 @@ bool timing_acquire(int kind, hipEvent_t* start, hipEvent_t* stop) {
     return true;
 }
 }  // namespace fdtd
+
+namespace {
+
+template <class Enqueue>
+int run_sequence(uint64_t key, hipStream_t s, Enqueue&& enqueue, const char* what) {
+    bool use_graph;
+    {
+        std::lock_guard<std::mutex> lk(g_graphs.mu);
+        use_graph = g_graphs.enabled && !g_timing.enabled;
+    }
+    int dev = 0;
+    if (use_graph && (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)) use_graph = false;
+    if (!use_graph) {
+        enqueue(s);
+        return check_hip(what);
+    }
+    key = fnv1a(key, &dev, sizeof dev);
+    std::lock_guard<std::mutex> lk(g_graphs.mu);
+    for (size_t i = 0; i < g_graphs.entries.size(); ++i) {
+        if (g_graphs.entries[i].first == key) {
+            if (hipGraphLaunch(g_graphs.entries[i].second, s) != hipSuccess)
+                return fail(FDTD_EHIP, "%s: graph launch failed", what);
+            return check_hip(what);
+        }
+    }
+    hipStream_t& cap = g_graphs.capture[dev];
+    if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+        cap = nullptr;
+        enqueue(s);
+        return check_hip(what);
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(FDTD_EHIP, "%s: stream capture could not start", what);
+    enqueue(cap);
+    const hipError_t ce = hipStreamEndCapture(cap, &graph);
+    if (ce != hipSuccess || !graph) return fail(FDTD_EHIP, "%s: stream capture failed: %s", what, hipGetErrorString(ce));
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) return fail(FDTD_EHIP, "%s: graph instantiation failed: %s", what, hipGetErrorString(ie));
+    if (g_graphs.entries.size() >= kMaxGraphs) {
+        hipGraphExecDestroy(g_graphs.entries.front().second);
+        g_graphs.entries.erase(g_graphs.entries.begin());
+    }
+    g_graphs.entries.emplace_back(key, exec);
+    if (hipGraphLaunch(exec, s) != hipSuccess) return fail(FDTD_EHIP, "%s: graph launch failed", what);
+    return check_hip(what);
+}
+
+uint64_t call_key(const Plan& pl, int dir, const fdtd_store_cfg_t* cfg, std::initializer_list<const void*> ptrs) {
+    uint64_t h = fnv1a(pl.hash, &dir, sizeof dir);
+    h = fnv1a(h, cfg, sizeof *cfg);
+    for (const void* p : ptrs) h = fnv1a(h, &p, sizeof p);
+    return h;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -281,20 +386,30 @@ int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const 
         return fail(FDTD_EHIP, "fdtd_forward: upload of coefficient tables failed");
 
     const int64_t N = g.N;
-    float* E = fields;
-    float* H = fields + 3 * N;
-    launch_fill(fields, 6 * N, 0.0f, s);
-    launch_fill(psi, (long long)pl.psi_floats, 0.0f, s);
     const int T = prob->steps, k = cfg->k;
+    // ping-pong field buffers; the parity of T picks the start so that the
+    // final state lands in the caller's buffer
+    float* F[2] = {fields, (float*)(ws + pl.ws_fields)};
+    const int start = T & 1;
     const bool fp8 = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED && g.vps > 0;
-    for (int n = 0; n < T; ++n) {
-        const int slice = ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1;
-        launch_fwd_h(g, E, H, psi, store, staging, slice, s);
-        launch_fwd_e(g, E, H, eps, psi, prob->src_wave[n], partials + (int64_t)n * pl.per_step, s);
-        if (slice >= 0 && fp8) launch_rec_quant(g, staging, store, slice, s);
-    }
-    launch_loss_final(partials, T, pl.per_step, loss, loss_series, s);
-    rc = check_hip("fdtd_forward");
+    const float* wave = prob->src_wave;
+    auto enqueue = [&](hipStream_t q) {
+        launch_fill(F[start], 6 * N, 0.0f, q);
+        launch_fill(psi, 2 * (long long)pl.psi_floats, 0.0f, q);
+        for (int n = 0; n < T; ++n) {
+            const int slice = ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1;
+            const float* in = F[(start + n) & 1];
+            float* out = F[(start + n + 1) & 1];
+            const float* psiH0 = psi + (n & 1) * pl.psi_floats;
+            float* psiH1 = psi + ((n + 1) & 1) * pl.psi_floats;
+            launch_fwd_step(g, pl.fwd, in, in + 3 * N, out, out + 3 * N, psiH0, psiH1, psi, eps, wave[n],
+                            partials + (int64_t)n * pl.per_step, store, staging, slice, q);
+            if (slice >= 0 && fp8) launch_rec_quant(g, staging, store, slice, q);
+        }
+        launch_loss_final(partials, T, pl.per_step, loss, loss_series, q);
+    };
+    rc = run_sequence(call_key(pl, 0, cfg, {eps, fields, psi, store, workspace, loss, loss_series}), s, enqueue,
+                      "fdtd_forward");
     if (rc) return rc;
     rec->problem_hash = pl.hash;
     rec->dtype = cfg->dtype;
@@ -324,20 +439,32 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
     g.src_profile = (const float*)(ws + pl.ws_profile);
 
     const int T = prob->steps, k = cfg->k;
+    const int64_t N = g.N;
+    float* Fp[2] = {fields, (float*)(ws + pl.ws_fields)};                       // primal
+    float* Fa[2] = {adj_fields, (float*)(ws + pl.ws_fields + pl.info.fields_bytes)};   // adjoint
     float* psi_buf[2] = {adj_psi, adj_psi + pl.psi_floats};
-    launch_fill(adj_psi, 2 * (long long)pl.psi_floats, 0.0f, s);
-    launch_fill_f64(grad_eps, (long long)pl.info.design_cells, 0.0, s);
-    launch_rev_init(g, fields, adj_fields, store, interp_for(T - 1, T, k), s);
-    int cur = 0;
-    for (int n = T - 1; n >= 0; --n) {
-        launch_rev_e(g, fields, eps, adj_fields, psi_buf[cur], psi_buf[1 - cur], store, interp_for(n, T, k),
-                     prob->src_wave[n], grad_eps, s);
-        const Interp qh = n >= 1 ? interp_for(n - 1, T, k) : Interp{-1, 0, 0.0f, 0.0f};
-        launch_rev_h(g, fields, adj_fields, psi_buf[cur], psi_buf[1 - cur], store, qh, n >= 1, n >= 1, s);
-        cur = 1 - cur;
-    }
-    if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, s);
-    rc = check_hip("fdtd_backward");
+    const float* wave = prob->src_wave;
+    auto enqueue = [&](hipStream_t q) {
+        launch_fill(Fa[0], 6 * N, 0.0f, q);
+        launch_fill(adj_psi, 2 * (long long)pl.psi_floats, 0.0f, q);
+        launch_fill_f64(grad_eps, (long long)pl.info.design_cells, 0.0, q);
+        launch_inject_h(g, Fp[0] + 3 * N, store, interp_for(T - 1, T, k), q);
+        for (int n = T - 1; n >= 0; --n) {
+            const int st = T - 1 - n;
+            float* po = Fp[st & 1];
+            float* pn = Fp[(st + 1) & 1];
+            float* ao = Fa[st & 1];
+            float* an = Fa[(st + 1) & 1];
+            const Interp qh = n >= 1 ? interp_for(n - 1, T, k) : Interp{-1, 0, 0.0f, 0.0f};
+            launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, po, po + 3 * N, pn, pn + 3 * N, eps, ao, store,
+                            interp_for(n, T, k), qh, n >= 1, wave[n], grad_eps, q);
+            launch_adj_step(g, pl.fwd, ao, ao + 3 * N, an, an + 3 * N, po, eps, psi_buf[st & 1],
+                            psi_buf[(st + 1) & 1], q);
+        }
+        if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, q);
+    };
+    rc = run_sequence(call_key(pl, 1, cfg, {eps, fields, store, workspace, adj_fields, adj_psi, grad_scale, grad_eps}),
+                      s, enqueue, "fdtd_backward");
     if (rc) return rc;
     rec->consumed = 1;
     return FDTD_OK;
@@ -345,7 +472,7 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
 
 int fdtd_codec_roundtrip(int32_t dtype, const float* values, int64_t n_blocks, int64_t block_len, void* codes,
                          float* scales, float* decoded, void* stream) {
-    if (dtype < FDTD_STORE_FP32 || dtype > FDTD_STORE_FP8_E4M3_SCALED)
+    if (dtype < FDTD_STORE_FP32 || dtype > FDTD_STORE_FP8_E4M3FN)
         return fail(FDTD_ESTORE, "unknown storage type %d", dtype);
     if (n_blocks < 0 || block_len < 0 || n_blocks > 0x7fffffff)
         return fail(FDTD_EINVAL, "fdtd_codec_roundtrip: bad block count or length");
@@ -354,6 +481,12 @@ int fdtd_codec_roundtrip(int32_t dtype, const float* values, int64_t n_blocks, i
         return fail(FDTD_EINVAL, "fdtd_codec_roundtrip: NULL buffer");
     launch_codec_roundtrip(dtype, values, n_blocks, block_len, codes, scales, decoded, (hipStream_t)stream);
     return check_hip("fdtd_codec_roundtrip");
+}
+
+int fdtd_set_graphs(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_graphs.mu);
+    g_graphs.enabled = enable != 0;
+    return FDTD_OK;
 }
 
 int fdtd_timing_enable(int32_t enable) {

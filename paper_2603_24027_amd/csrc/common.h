@@ -111,35 +111,58 @@ __host__ __device__ inline float dec_fp16(uint16_t h) {
     return u2f(sign | ((e - 15 + 127) << 23) | (m << 13));
 }
 
-// OCP FP8 E4M3 (bias 7, max 448, S.1111.111 = NaN, no infinity).  Values past
-// the rounding threshold of 448 map to NaN (non-saturating); the scaled
-// recorder never produces them.
-__host__ __device__ inline uint8_t enc_e4m3(float x) {
-    uint32_t u = f2u(x);
+// 8-bit floats with E exponent bits, M mantissa bits and exponent bias B,
+// round to nearest even.  KIND 0: IEEE-style (top exponent holds inf / NaN);
+// KIND 1: "fn" (finite, only S.1..1.1..1 is NaN); KIND 2: "fnuz" (finite, the
+// negative-zero pattern 0x80 is NaN, zero is unsigned).  Past the largest
+// finite value the result is inf (KIND 0) or NaN (KIND 1, 2), as a
+// non-saturating conversion gives.
+template <int E, int M, int B, int KIND>
+__host__ __device__ inline uint8_t enc_f8(float x) {
+    constexpr uint32_t EMAX = (1u << E) - 1, MMASK = (1u << M) - 1;
+    constexpr uint32_t MAXCODE = KIND == 0 ? (((EMAX - 1) << M) | MMASK) : (KIND == 1 ? ((EMAX << M) | (MMASK - 1)) : 0x7fu);
+    const uint32_t u = f2u(x);
     uint32_t sign = (u >> 24) & 0x80u;
-    uint32_t a = u & 0x7fffffffu;
-    if (a > 0x7f800000u) return (uint8_t)(sign | 0x7fu);
-    float af = u2f(a);
-    if (af > 464.0f) return (uint8_t)(sign | 0x7fu);
-    if (af < 0.015625f) {                                            // below 2^-6: subnormal
-        float q = rintf(af * 512.0f);                                // value = q * 2^-9
-        return (uint8_t)(sign | (uint32_t)q);                        // q = 8 -> min normal
+    const uint32_t a = u & 0x7fffffffu;
+    if (a > 0x7f800000u)                                              // NaN
+        return KIND == 2 ? 0x80u : (KIND == 1 ? (uint8_t)(sign | 0x7fu) : (uint8_t)(sign | (EMAX << M) | (1u << (M - 1))));
+    const int e = (int)(a >> 23) - 127;
+    uint32_t code;
+    if (e < 1 - B) {                                                  // below the smallest normal: subnormal
+        const float q = rintf(u2f(a) * u2f((uint32_t)(B - 1 + M + 127) << 23));   // |x| / 2^(1-B-M), exact
+        code = (uint32_t)q;                                           // q = 2^M is the smallest normal
+    } else if (e + B > (int)EMAX + 1) {
+        code = MAXCODE + 1;                                           // far past the range
+    } else {
+        const uint32_t mant = a & 0x7fffffu;
+        code = ((uint32_t)(e + B) << M) | (mant >> (23 - M));
+        const uint32_t rem = mant & ((1u << (23 - M)) - 1), half = 1u << (22 - M);
+        if (rem > half || (rem == half && (code & 1u))) code += 1u;
     }
-    int e = (int)(a >> 23) - 127;
-    uint32_t mant = a & 0x7fffffu;
-    uint32_t code = ((uint32_t)(e + 7) << 3) | (mant >> 20);
-    uint32_t rem = mant & 0xfffffu;
-    if (rem > 0x80000u || (rem == 0x80000u && (code & 1u))) code += 1u;
+    if (code > MAXCODE) {
+        if (KIND == 0) return (uint8_t)(sign | (EMAX << M));
+        return KIND == 1 ? (uint8_t)(sign | 0x7fu) : 0x80u;
+    }
+    if (KIND == 2 && code == 0) sign = 0;
     return (uint8_t)(sign | code);
 }
-__host__ __device__ inline float dec_e4m3(uint8_t c) {
-    uint32_t sign = ((uint32_t)c & 0x80u) << 24;
-    uint32_t e = (c >> 3) & 0xfu, m = c & 7u;
-    if (e == 15 && m == 7) return u2f(sign | 0x7fc00000u);
-    float v = (e == 0) ? (float)m * 0.001953125f                     // m * 2^-9
-                       : u2f(((e - 7 + 127) << 23) | (m << 20));
+
+template <int E, int M, int B, int KIND>
+__host__ __device__ inline float dec_f8(uint8_t c) {
+    constexpr uint32_t EMAX = (1u << E) - 1, MMASK = (1u << M) - 1;
+    const uint32_t sign = ((uint32_t)c & 0x80u) << 24;
+    const uint32_t e = (c >> M) & EMAX, m = c & MMASK;
+    if (KIND == 2 && c == 0x80u) return u2f(0x7fc00000u);
+    if (KIND == 1 && e == EMAX && m == MMASK) return u2f(sign | 0x7fc00000u);
+    if (KIND == 0 && e == EMAX) return u2f(sign | (m ? 0x7fc00000u : 0x7f800000u));
+    const float v = e == 0 ? (float)m * u2f((uint32_t)(127 + 1 - B - M) << 23)          // m 2^(1-B-M)
+                           : u2f(((e + 127 - B) << 23) | (m << (23 - M)));
     return u2f(f2u(v) | sign);
 }
+
+// OCP E4M3 (bias 7, max 448): the type of the scaled recorder.
+__host__ __device__ inline uint8_t enc_e4m3(float x) { return enc_f8<4, 3, 7, 1>(x); }
+__host__ __device__ inline float dec_e4m3(uint8_t c) { return dec_f8<4, 3, 7, 1>(c); }
 
 // Power-of-two scale exponent: smallest e with 448 * 2^e >= m, clamped to [-126, 127].
 __host__ __device__ inline int fp8_scale_exp(float m) {
@@ -172,17 +195,40 @@ __host__ __device__ inline float pow2f(int e) {   // 2^e for e in [-126, 127]
 }
 
 inline __host__ __device__ int storage_bytes(int dtype) {
-    return dtype == 0 ? 4 : (dtype == 3 ? 1 : 2);
+    return dtype == 0 ? 4 : (dtype <= 2 ? 2 : 1);
 }
 
-// Decode one stored value (FP8 needs its block scale).
+// Storage types 4..9: the unscaled 8-bit types of the paper's comparison.
+__device__ inline uint8_t enc_unscaled(int dtype, float v) {
+    switch (dtype) {
+        case 4: return enc_f8<4, 3, 11, 2>(v);   // e4m3b11fnuz
+        case 5: return enc_f8<5, 2, 16, 2>(v);   // e5m2fnuz
+        case 6: return enc_f8<4, 3, 8, 2>(v);    // e4m3fnuz
+        case 7: return enc_f8<4, 3, 7, 0>(v);    // e4m3 (IEEE-style)
+        case 8: return enc_f8<3, 4, 3, 0>(v);    // e3m4 (IEEE-style)
+        default: return enc_f8<4, 3, 7, 1>(v);   // e4m3fn
+    }
+}
+__device__ inline float dec_unscaled(int dtype, uint8_t c) {
+    switch (dtype) {
+        case 4: return dec_f8<4, 3, 11, 2>(c);
+        case 5: return dec_f8<5, 2, 16, 2>(c);
+        case 6: return dec_f8<4, 3, 8, 2>(c);
+        case 7: return dec_f8<4, 3, 7, 0>(c);
+        case 8: return dec_f8<3, 4, 3, 0>(c);
+        default: return dec_f8<4, 3, 7, 1>(c);
+    }
+}
+
+// Decode one stored value (the scaled FP8 type needs its block scale).
 __device__ inline float load_code(const void* store, long long byte_slice, long long off, int dtype, float scale) {
     const char* base = (const char*)store + byte_slice;
     switch (dtype) {
         case 0: return ((const float*)base)[off];
         case 1: return dec_fp16(((const uint16_t*)base)[off]);
         case 2: return dec_bf16(((const uint16_t*)base)[off]);
-        default: return dec_e4m3(((const uint8_t*)base)[off]) * scale;
+        case 3: return dec_e4m3(((const uint8_t*)base)[off]) * scale;
+        default: return dec_unscaled(dtype, ((const uint8_t*)base)[off]);
     }
 }
 
@@ -192,7 +238,8 @@ __device__ inline void store_code(void* store, long long byte_slice, long long o
         case 0: ((float*)base)[off] = v; break;
         case 1: ((uint16_t*)base)[off] = enc_fp16(v); break;
         case 2: ((uint16_t*)base)[off] = enc_bf16(v); break;
-        default: break;   // FP8 goes through the staging buffer and the quantiser kernel
+        case 3: break;   // the scaled FP8 type goes through the staging buffer and the quantiser kernel
+        default: ((uint8_t*)base)[off] = enc_unscaled(dtype, v); break;
     }
 }
 
@@ -265,7 +312,7 @@ __device__ inline int slab_coord(int i, int n, int P) {   // -1 outside the slab
 // is the kernel's execution and no extra packet enters the stream.
 // ----------------------------------------------------------------------------
 enum KernelKind {
-    K_FILL = 0, K_FWD_H, K_FWD_E, K_REC_QUANT, K_LOSS_FINAL, K_REV_INIT, K_REV_E, K_REV_H, K_SCALE_GRAD,
+    K_FILL = 0, K_FWD_STEP, K_REC_QUANT, K_LOSS_FINAL, K_INJECT, K_PRIM_REV, K_ADJ_STEP, K_SCALE_GRAD,
     K_CODEC, K_NUM_KINDS
 };
 
@@ -284,18 +331,19 @@ inline void launch_kernel(int kind, Kernel kernel, dim3 grid, dim3 block, hipStr
 // Launch wrappers (defined with the kernels)
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_fill_f64(double* p, long long n, double v, hipStream_t s);
-void launch_fwd_h(const Grid& g, const float* E, float* H, float* psi, void* store, float* staging,
-                  int slice, hipStream_t s);
-void launch_fwd_e(const Grid& g, float* E, const float* H, const float* eps, float* psi, float wave,
-                  double* partials, hipStream_t s);
+struct Tiling;
+void launch_fwd_step(const Grid& g, const Tiling& t, const float* E0, const float* H0, float* E1, float* H1,
+                     const float* psiH0, float* psiH1, float* psiE, const float* eps, float wave, double* partials,
+                     void* store, float* staging, int slice, hipStream_t s);
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s);
 void launch_loss_final(const double* partials, int steps, int per_step, double* loss, double* series,
                        hipStream_t s);
-void launch_rev_init(const Grid& g, float* fields, float* adj, const void* store, Interp q, hipStream_t s);
-void launch_rev_e(const Grid& g, float* fields, const float* eps, float* adj, const float* psi_in,
-                  float* psi_out, const void* store, Interp q, float wave, double* grad, hipStream_t s);
-void launch_rev_h(const Grid& g, float* fields, float* adj, const float* psi_in, float* psi_out,
-                  const void* store, Interp q, int inject, int seed, hipStream_t s);
+void launch_inject_h(const Grid& g, float* H, const void* store, Interp q, hipStream_t s);
+void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], const float* E0,
+                     const float* H0, float* E1, float* H1, const float* eps, const float* Eb0, const void* store,
+                     Interp qE, Interp qH, int inject_h, float wave, double* grad, hipStream_t s);
+void launch_adj_step(const Grid& g, const Tiling& t, const float* Eb0, const float* Hb0, float* Eb1, float* Hb1,
+                     const float* Es, const float* eps, const float* psi_in, float* psi_out, hipStream_t s);
 void launch_scale_grad(double* grad, long long n, const double* scale, hipStream_t s);
 void launch_codec_roundtrip(int dtype, const float* values, long long n_blocks, long long block_len,
                             void* codes, float* scales, float* decoded, hipStream_t s);

@@ -22,8 +22,14 @@ STORE_DTYPES = {
     "fp16": _lib.STORE_FP16,
     "bf16": _lib.STORE_BF16,
     "fp8_e4m3_scaled": _lib.STORE_FP8_E4M3_SCALED,
+    "fp8_e4m3b11fnuz": _lib.STORE_FP8_E4M3B11FNUZ,
+    "fp8_e5m2fnuz": _lib.STORE_FP8_E5M2FNUZ,
+    "fp8_e4m3fnuz": _lib.STORE_FP8_E4M3FNUZ,
+    "fp8_e4m3": _lib.STORE_FP8_E4M3,
+    "fp8_e3m4": _lib.STORE_FP8_E3M4,
+    "fp8_e4m3fn": _lib.STORE_FP8_E4M3FN,
 }
-STORAGE_BITS = {"fp32": 32, "fp16": 16, "bf16": 16, "fp8_e4m3_scaled": 8}
+STORAGE_BITS = {name: (32 if name == "fp32" else 16 if name in ("fp16", "bf16") else 8) for name in STORE_DTYPES}
 
 
 def _i3(v):
@@ -196,6 +202,11 @@ def codec_roundtrip(values: torch.Tensor, dtype: str, n_blocks: int):
                                       codes.data_ptr(), scales.data_ptr(), decoded.data_ptr(),
                                       _stream_handle(values.device)))
     return codes, scales[:n_blocks], decoded
+
+
+def set_graphs(on: bool = True):
+    """Replay repeated forward/backward calls as HIP graphs (default) or enqueue every launch."""
+    check(load().fdtd_set_graphs(1 if on else 0))
 
 
 def timing_enable(on: bool = True):

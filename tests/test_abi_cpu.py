@@ -46,7 +46,9 @@ def test_store_config_matches_closed_form(name):
     kw = {"steps": 8} if name in ("c4", "c5") else {}
     prob = w.make(name, **kw)
     p = pk.Problem(prob)
-    for dtype, mode in [("fp32", "fp32"), ("fp16", "fp16"), ("bf16", "bf16"), ("fp8_e4m3_scaled", "fp8_e4m3fn_scaled")]:
+    modes = [("fp32", "fp32"), ("fp16", "fp16"), ("bf16", "bf16"), ("fp8_e4m3_scaled", "fp8_e4m3fn_scaled")]
+    modes += [(m, m) for m in ("fp8_e4m3b11fnuz", "fp8_e5m2fnuz", "fp8_e4m3fnuz", "fp8_e4m3", "fp8_e3m4", "fp8_e4m3fn")]
+    for dtype, mode in modes:
         for k in (1, 3, 16):
             info = pk.store_config(p, dtype, k)
             pay, sc = ostore.storage_bytes(prob.nx, prob.ny, prob.nz, prob.pml, prob.steps, k, mode)
@@ -112,7 +114,8 @@ def test_backward_record_checks():
 
 def test_codec_entry_validation():
     lib = pk.load()
-    assert lib.fdtd_codec_roundtrip(9, None, 1, 1, None, None, None, None) == _lib.FDTD_ESTORE
+    assert lib.fdtd_codec_roundtrip(10, None, 1, 1, None, None, None, None) == _lib.FDTD_ESTORE
+    assert lib.fdtd_codec_roundtrip(-1, None, 1, 1, None, None, None, None) == _lib.FDTD_ESTORE
     assert lib.fdtd_codec_roundtrip(0, None, -1, 1, None, None, None, None) == _lib.FDTD_EINVAL
     assert lib.fdtd_codec_roundtrip(3, None, 1, 4, None, None, None, None) == _lib.FDTD_EINVAL
     assert lib.fdtd_codec_roundtrip(0, None, 0, 4, None, None, None, None) == _lib.FDTD_OK
