@@ -15,7 +15,7 @@ SOURCES = ["api.hip", "forward.hip", "reverse.hip"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
-    "-std=c++17",
+    "-std=c++20",
     "-fPIC",
     "-fvisibility=hidden",
     # packed FP32 instructions stay off in all device code

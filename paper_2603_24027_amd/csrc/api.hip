@@ -97,9 +97,9 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     if (!p || !cfg) return fail(FDTD_EINVAL, "problem and store config must not be NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(FDTD_EINVAL, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
-    // kernels index one field buffer (6 components) with 32-bit offsets
-    if (p->ny > 4 * 65535 || p->nz > 65535 || 6 * (int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
-        return fail(FDTD_EINVAL, "grid too large: 6 * cells must stay below 2^31");
+    // kernels address a 3-component field as one buffer with 32-bit byte offsets below 2^31
+    if (p->ny > 4 * 65535 || p->nz > 65535 || 12 * (int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
+        return fail(FDTD_EINVAL, "grid too large: 12 * cells must stay below 2^31");
     if (p->steps < 1) return fail(FDTD_EINVAL, "steps must be >= 1 (got %d)", p->steps);
     if (p->pml < 0 || p->pml > FDTD_MAX_PML) return fail(FDTD_EINVAL, "pml must be in [0, %d]", FDTD_MAX_PML);
     const int n[3] = {p->nx, p->ny, p->nz};
@@ -160,7 +160,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     g.dbz0 = p->det_lo[2];      g.dnbz = p->det_hi[2] - p->det_lo[2];
     Tiling& t = pl->fwd;
     t.ty = env_int("FDTD_TILE_Y", 8) == 4 ? 4 : 8;
-    t.cz = std::max(1, std::min(env_int("FDTD_TILE_Z", 8), p->nz));
+    t.cz = env_int("FDTD_TILE_Z", 8) == 4 ? 4 : 8;
     t.ntx = (p->nx + TX - 1) / TX;
     t.nty = (p->ny + t.ty - 1) / t.ty;
     t.ntz = (p->nz + t.cz - 1) / t.cz;
@@ -458,7 +458,7 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
             const Interp qh = n >= 1 ? interp_for(n - 1, T, k) : Interp{-1, 0, 0.0f, 0.0f};
             launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, po, po + 3 * N, pn, pn + 3 * N, eps, ao, store,
                             interp_for(n, T, k), qh, n >= 1, wave[n], grad_eps, q);
-            launch_adj_step(g, pl.fwd, ao, ao + 3 * N, an, an + 3 * N, po, eps, psi_buf[st & 1],
+            launch_adj_step(g, pl.fwd, ao, ao + 3 * N, an, an + 3 * N, eps, psi_buf[st & 1],
                             psi_buf[(st + 1) & 1], q);
         }
         if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, q);

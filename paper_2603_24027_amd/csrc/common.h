@@ -254,12 +254,14 @@ __device__ inline void store_code(void* store, long long byte_slice, long long o
 // each over the interior extent of the other two axes.
 // ----------------------------------------------------------------------------
 __host__ __device__ inline long long block_offset(const Grid& g, int b) {
-    long long ax = (long long)g.my * g.mz, ay = (long long)g.mx * g.mz, az = (long long)g.mx * g.my;
-    long long face[6] = {0, 2 * ax, 2 * ax + 2 * ay, 2 * (ax + ay + az), 2 * (ax + ay + az) + 2 * ax,
-                         2 * (ax + ay + az) + 2 * ax + 2 * ay};
-    long long area[3] = {ax, ay, az};
-    int f = b >> 1;
-    return face[f] + (b & 1) * area[f % 3];
+    // blocks 2f, 2f+1 of face f (x-, y-, z- low faces, then x+, y+, z+ high faces),
+    // each as large as that face's plane; written without a local table so that a
+    // run-time block index stays in registers
+    const long long ax = (long long)g.my * g.mz, ay = (long long)g.mx * g.mz, az = (long long)g.mx * g.my;
+    const int f = b >> 1, a = f % 3;
+    const long long face = (f >= 3 ? 2 * (ax + ay + az) : 0) + (a >= 1 ? 2 * ax : 0) + (a >= 2 ? 2 * ay : 0);
+    const long long area = a == 0 ? ax : (a == 1 ? ay : az);
+    return face + (b & 1) * area;
 }
 
 __host__ __device__ inline long long block_len(const Grid& g, int b) {
@@ -284,6 +286,97 @@ __device__ inline float shell_value(const Grid& g, const void* store, const Inte
         v += q.w0 * load_code(store, q.j0 * g.slice_stride, o, g.dtype, s0);
     }
     return v;
+}
+
+// Compile-time storage type versions (the sweeps are instantiated per type so
+// that no conversion code other than the one in use enters a kernel).
+template <int DT>
+__device__ inline float load_code_t(const void* store, long long byte_slice, long long off, float scale) {
+    const char* base = (const char*)store + byte_slice;
+    if constexpr (DT == 0) return ((const float*)base)[off];
+    else if constexpr (DT == 1) return dec_fp16(((const uint16_t*)base)[off]);
+    else if constexpr (DT == 2) return dec_bf16(((const uint16_t*)base)[off]);
+    else if constexpr (DT == 3) return dec_e4m3(((const uint8_t*)base)[off]) * scale;
+    else if constexpr (DT == 4) return dec_f8<4, 3, 11, 2>(((const uint8_t*)base)[off]);
+    else if constexpr (DT == 5) return dec_f8<5, 2, 16, 2>(((const uint8_t*)base)[off]);
+    else if constexpr (DT == 6) return dec_f8<4, 3, 8, 2>(((const uint8_t*)base)[off]);
+    else if constexpr (DT == 7) return dec_f8<4, 3, 7, 0>(((const uint8_t*)base)[off]);
+    else if constexpr (DT == 8) return dec_f8<3, 4, 3, 0>(((const uint8_t*)base)[off]);
+    else return dec_f8<4, 3, 7, 1>(((const uint8_t*)base)[off]);
+}
+
+// Record one value of a kept step: the scaled FP8 type goes to the FP32 staging
+// buffer (quantised per block afterwards), every other type straight to the store.
+template <int DT>
+__device__ inline void record_t(void* store, float* staging, long long byte_slice, long long off, float v) {
+    char* base = (char*)store + byte_slice;
+    if constexpr (DT == 0) ((float*)base)[off] = v;
+    else if constexpr (DT == 1) ((uint16_t*)base)[off] = enc_fp16(v);
+    else if constexpr (DT == 2) ((uint16_t*)base)[off] = enc_bf16(v);
+    else if constexpr (DT == 3) staging[off] = v;
+    else if constexpr (DT == 4) ((uint8_t*)base)[off] = enc_f8<4, 3, 11, 2>(v);
+    else if constexpr (DT == 5) ((uint8_t*)base)[off] = enc_f8<5, 2, 16, 2>(v);
+    else if constexpr (DT == 6) ((uint8_t*)base)[off] = enc_f8<4, 3, 8, 2>(v);
+    else if constexpr (DT == 7) ((uint8_t*)base)[off] = enc_f8<4, 3, 7, 0>(v);
+    else if constexpr (DT == 8) ((uint8_t*)base)[off] = enc_f8<3, 4, 3, 0>(v);
+    else ((uint8_t*)base)[off] = enc_f8<4, 3, 7, 1>(v);
+}
+
+// Record one value of a kept step through a range-checked buffer store (dropped
+// when the offset is OOB): the scaled FP8 type goes to the FP32 staging buffer,
+// every other type straight to the store.  `st` covers the kept step's slice of
+// the store, `elem` is the element index within it (block offset + position).
+template <int DT>
+__device__ inline void record_b(__amdgpu_buffer_rsrc_t st, __amdgpu_buffer_rsrc_t stg, long long elem, bool on,
+                                float v) {
+    const uint32_t oob = 0x80000000u;
+    if constexpr (DT == 3) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), stg, on ? (uint32_t)(elem * 4) : oob, 0, 0);
+    } else if constexpr (DT == 0) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), st, on ? (uint32_t)(elem * 4) : oob, 0, 0);
+    } else if constexpr (DT == 1 || DT == 2) {
+        const uint16_t q = DT == 1 ? enc_fp16(v) : enc_bf16(v);
+        __builtin_amdgcn_raw_buffer_store_b16(q, st, on ? (uint32_t)(elem * 2) : oob, 0, 0);
+    } else {
+        uint8_t q;
+        if constexpr (DT == 4) q = enc_f8<4, 3, 11, 2>(v);
+        else if constexpr (DT == 5) q = enc_f8<5, 2, 16, 2>(v);
+        else if constexpr (DT == 6) q = enc_f8<4, 3, 8, 2>(v);
+        else if constexpr (DT == 7) q = enc_f8<4, 3, 7, 0>(v);
+        else if constexpr (DT == 8) q = enc_f8<3, 4, 3, 0>(v);
+        else q = enc_f8<4, 3, 7, 1>(v);
+        __builtin_amdgcn_raw_buffer_store_b8(q, st, on ? (uint32_t)elem : oob, 0, 0);
+    }
+}
+
+template <int DT>
+__device__ inline float shell_value_t(const Grid& g, const void* store, const Interp& q, int b, long long off) {
+    const long long o = block_offset(g, b) + off;
+    const float* scales = (const float*)((const char*)store + g.scale_off);
+    const float s1 = DT == 3 ? scales[q.j1 * 12 + b] : 1.0f;
+    float v = q.w1 * load_code_t<DT>(store, q.j1 * g.slice_stride, o, s1);
+    if (q.j0 >= 0) {
+        const float s0 = DT == 3 ? scales[q.j0 * 12 + b] : 1.0f;
+        v += q.w0 * load_code_t<DT>(store, q.j0 * g.slice_stride, o, s0);
+    }
+    return v;
+}
+
+// Calls f.template operator()<DT>() with the storage type as a compile-time constant.
+template <class F>
+inline void with_dtype(int dtype, F&& f) {
+    switch (dtype) {
+        case 0: f.template operator()<0>(); break;
+        case 1: f.template operator()<1>(); break;
+        case 2: f.template operator()<2>(); break;
+        case 3: f.template operator()<3>(); break;
+        case 4: f.template operator()<4>(); break;
+        case 5: f.template operator()<5>(); break;
+        case 6: f.template operator()<6>(); break;
+        case 7: f.template operator()<7>(); break;
+        case 8: f.template operator()<8>(); break;
+        default: f.template operator()<9>(); break;
+    }
 }
 
 __device__ inline bool in_box(int i, int j, int k, const int lo[3], const int hi[3]) {
@@ -340,10 +433,10 @@ void launch_loss_final(const double* partials, int steps, int per_step, double* 
                        hipStream_t s);
 void launch_inject_h(const Grid& g, float* H, const void* store, Interp q, hipStream_t s);
 void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], const float* E0,
-                     const float* H0, float* E1, float* H1, const float* eps, const float* Eb0, const void* store,
+                     const float* H0, float* E1, float* H1, const float* eps, float* Eb0, const void* store,
                      Interp qE, Interp qH, int inject_h, float wave, double* grad, hipStream_t s);
 void launch_adj_step(const Grid& g, const Tiling& t, const float* Eb0, const float* Hb0, float* Eb1, float* Hb1,
-                     const float* Es, const float* eps, const float* psi_in, float* psi_out, hipStream_t s);
+                     const float* eps, const float* psi_in, float* psi_out, hipStream_t s);
 void launch_scale_grad(double* grad, long long n, const double* scale, hipStream_t s);
 void launch_codec_roundtrip(int dtype, const float* values, long long n_blocks, long long block_len,
                             void* codes, float* scales, float* decoded, hipStream_t s);

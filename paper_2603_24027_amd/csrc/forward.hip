@@ -1,14 +1,12 @@
 // Forward Yee step with convolutional PML, interface recorder and detector loss (gfx950).
 //
-// One step n is two sweeps over the grid (one thread per cell, x fastest,
-// 64 x 4 threads per block):
-//   fwd_h  H^{n+1/2} = H^{n-1/2} - dt curl E^n         (forward differences)
-//          and, on kept steps, the interface shell: E^n on the high faces and
-//          H^{n+1/2} on the low faces (Section 2: the interface slices are
-//          recorded during the forward simulation)
-//   fwd_e  E^{n+1} = E^n + (dt / eps)(curl H^{n+1/2} - J^n)  (backward differences)
-//          and the per-block FP64 partial of sum_D |E^{n+1}|^2
-// The PML recursions psi <- b psi + a g run only inside the slabs.
+// One step n is one fused z-marching sweep (march.h):
+//   H^{n+1/2} = H^{n-1/2} - dt curl E^n              (forward differences)
+//   E^{n+1}   = E^n + (dt / eps)(curl H^{n+1/2} - J^n)  (backward differences)
+// with the CPML recursions psi <- b psi + a g inside the slabs, on kept steps
+// the interface shell (E^n on the high faces and H^{n+1/2} on the low faces;
+// Section 2: the interface slices are recorded during the forward simulation)
+// and the per-tile FP64 partial of sum_D |E^{n+1}|^2.
 #include "march.h"
 
 namespace fdtd {
@@ -39,70 +37,196 @@ void launch_fill_f64(double* p, long long n, double v, hipStream_t s) {
     launch_kernel(K_FILL, k_fill_f64, dim3((unsigned)blocks), dim3(256), s, p, n, v);
 }
 
-// H^{n+1/2} at one cell from the LDS planes of E^n at z (cur) and z + 1 (nxt).
-// (ex, ey): extended-plane coordinates; (x, y, z): the cell's index inside the
-// domain.  PML auxiliaries are read from psi_in and, for the owning block,
-// written to psi_out (NULL for a recomputed halo cell).
+// The six curl-E differences of the H half at extended-plane position (ex, ey)
+// from the LDS planes of E^n at z (cur) and z + 1 (nxt).
 template <int TY>
-__device__ inline void h_cell(const Grid& g, const float (*cur)[TY + 2][EXT], const float (*nxt)[TY + 2][EXT],
-                              int ex, int ey, int x, int y, int z, const float* __restrict__ H0,
-                              const float* __restrict__ psi_in, float* __restrict__ psi_out,
-                              float& hx, float& hy, float& hz) {
+__device__ inline void h_terms(const float (*cur)[TY + 2][EXT], const float (*nxt)[TY + 2][EXT], int ex, int ey,
+                               float t[6]) {
     const float exc = cur[0][ey][ex], eyc = cur[1][ey][ex], ezc = cur[2][ey][ex];
-    float t0 = cur[2][ey + 1][ex] - ezc;   // (Hx, y, +, Ez)
-    float t1 = nxt[1][ey][ex] - eyc;       // (Hx, z, -, Ey)
-    float t2 = nxt[0][ey][ex] - exc;       // (Hy, z, +, Ex)
-    float t3 = cur[2][ey][ex + 1] - ezc;   // (Hy, x, -, Ez)
-    float t4 = cur[1][ey][ex + 1] - eyc;   // (Hz, x, +, Ey)
-    float t5 = cur[0][ey + 1][ex] - exc;   // (Hz, y, -, Ex)
-    const int P = g.P;
-    if (P > 0) {
-        const float* bH = g.coef + 6 * P;
-        const float* aH = g.coef + 8 * P;
-        const float* kH = g.coef + 10 * P;
-        int s = slab_coord(x, g.nx, P);
-        if (s >= 0) {
-            const int o = (int)g.psi_off[0] + s + 2 * P * (y + g.ny * z);
-            const float b = bH[s], a = aH[s], kv = kH[s];
-            const float p3 = b * psi_in[o] + a * t3;
-            const float p4 = b * psi_in[o + (int)g.slab[0]] + a * t4;
-            if (psi_out) { psi_out[o] = p3; psi_out[o + (int)g.slab[0]] = p4; }
-            t3 = kv * t3 + p3;
-            t4 = kv * t4 + p4;
-        }
-        s = slab_coord(y, g.ny, P);
-        if (s >= 0) {
-            const int o = (int)g.psi_off[1] + x + g.nx * (s + 2 * P * z);
-            const float b = bH[s], a = aH[s], kv = kH[s];
-            const float p0 = b * psi_in[o] + a * t0;
-            const float p5 = b * psi_in[o + (int)g.slab[1]] + a * t5;
-            if (psi_out) { psi_out[o] = p0; psi_out[o + (int)g.slab[1]] = p5; }
-            t0 = kv * t0 + p0;
-            t5 = kv * t5 + p5;
-        }
-        s = slab_coord(z, g.nz, P);
-        if (s >= 0) {
-            const int o = (int)g.psi_off[2] + x + g.nx * (y + g.ny * s);
-            const float b = bH[s], a = aH[s], kv = kH[s];
-            const float p1 = b * psi_in[o] + a * t1;
-            const float p2 = b * psi_in[o + (int)g.slab[2]] + a * t2;
-            if (psi_out) { psi_out[o] = p1; psi_out[o + (int)g.slab[2]] = p2; }
-            t1 = kv * t1 + p1;
-            t2 = kv * t2 + p2;
-        }
-    }
-    const int N = (int)g.N;
-    const int idx = x + g.nx * (y + g.ny * z);
+    t[0] = cur[2][ey + 1][ex] - ezc;   // (Hx, y, +, Ez)
+    t[1] = nxt[1][ey][ex] - eyc;       // (Hx, z, -, Ey)
+    t[2] = nxt[0][ey][ex] - exc;       // (Hy, z, +, Ex)
+    t[3] = cur[2][ey][ex + 1] - ezc;   // (Hy, x, -, Ez)
+    t[4] = cur[1][ey][ex + 1] - eyc;   // (Hz, x, +, Ey)
+    t[5] = cur[0][ey + 1][ex] - exc;   // (Hz, y, -, Ex)
+}
+
+// H^{n+1/2} = H^{n-1/2} - dt curl E with the H-side CPML; p holds the old auxiliaries
+// on entry and the new ones on return.
+__device__ inline void h_update(const Grid& g, const Col& c, int sz, float t[6], const float h0[3], float p[6],
+                                float h[3]) {
+    cpml_terms(g.coef + 6 * g.P, g.P, c, sz, t, p);
     const float dt = g.dt;
-    hx = H0[idx] - dt * (t0 - t1);
-    hy = H0[N + idx] - dt * (t2 - t3);
-    hz = H0[2 * N + idx] - dt * (t4 - t5);
+    h[0] = h0[0] - dt * (t[0] - t[1]);
+    h[1] = h0[1] - dt * (t[2] - t[3]);
+    h[2] = h0[2] - dt * (t[4] - t[5]);
+}
+
+// The same with the coefficients of the cell's three slabs given (branch-free CPML).
+__device__ inline void h_update_cf(float dt, const Cf& cx, const Cf& cy, const Cf& cz, float t[6], const float h0[3],
+                                   float p[6], float h[3]) {
+    cpml_apply(cx, cy, cz, t, p);
+    h[0] = h0[0] - dt * (t[0] - t[1]);
+    h[1] = h0[1] - dt * (t[2] - t[3]);
+    h[2] = h0[2] - dt * (t[4] - t[5]);
+}
+
+// Buffer resources of one forward sweep.
+struct FwdBufs {
+    rsrc_t E0, H0, E1, H1, eps, psiH0, psiH1, psiE, store, staging, src;
+};
+
+// Everything the forward sweep reads from memory for plane k of its column:
+// E^n of plane k+1 (own cell and the LDS-ring position), H^{n-1/2} of plane k
+// (own cell and the halo cell), eps, the source profile (0 outside the source box)
+// and the PML auxiliaries of plane k.
+struct PlaneIn {
+    float e1[3], er[3], h0[3], hh0[3], ep, sp;
+    float ph[6], pe[6], phh[6];
+};
+
+// Straight-line loads of plane k's inputs (out-of-domain and out-of-slab values read as 0).
+template <int TY>
+__device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, const FwdCtx<TY>& c, int k,
+                                              PlaneIn& d) {
+    const int N = c.N;
+    const int ok = k * c.plane;
+    const int z1 = bound(k + 1, g.nz, g.periodic);
+    const int o1 = z1 < 0 ? -1 : z1 * c.plane;
+    const int szk = g.P > 0 ? slab_coord(k, g.nz, g.P) : -1;
+    bld3(b.E0, (c.own.xy < 0 || o1 < 0) ? -1 : c.own.xy + o1, N, d.e1);
+    bld3(b.E0, (c.ring.xy < 0 || o1 < 0) ? -1 : c.ring.xy + o1, N, d.er);
+    bld3(b.H0, c.live ? c.own.xy + ok : -1, N, d.h0);
+    bld3(b.H0, c.hc.xy >= 0 ? c.hc.xy + ok : -1, N, d.hh0);
+    const float ep = bld(b.eps, c.live ? (uint32_t)(c.own.xy + ok) << 2 : OOB);
+    d.ep = c.live ? ep : 1.0f;
+    uint32_t so = OOB;
+    if (c.live && in_box(c.x, c.y, k, g.src_lo, g.src_hi)) {
+        const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
+        so = (uint32_t)((c.x - g.src_lo[0]) + sxn * ((c.y - g.src_lo[1]) + syn * (k - g.src_lo[2]))) << 2;
+    }
+    d.sp = bld(b.src, so);
+    int po[3];
+    psi_offsets(g, c.own, k, c.live ? szk : -1, 0, po);
+    if (!c.live) po[0] = po[1] = -1;
+    bld_psi(g, b.psiH0, po, d.ph);
+    psi_offsets(g, c.own, k, c.live ? szk : -1, 1, po);
+    if (!c.live) po[0] = po[1] = -1;
+    bld_psi(g, b.psiE, po, d.pe);
+    psi_offsets(g, c.hc, k, szk, 0, po);
+    bld_psi(g, b.psiH0, po, d.phh);
+}
+
+// One plane k of the forward sweep: publish E^n(k+1) to LDS, H^{n+1/2}(k) on the own
+// and halo cells, then E^{n+1}(k) on the own cell.  `in` holds the plane's inputs,
+// loaded one plane ahead.  All stores are unconditional buffer stores (dropped for
+// idle lanes and cells outside a slab).
+template <int TY, int REC, int CZ>
+__device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const FwdCtx<TY>& c,
+                                          float (*sE)[3][TY + 2][EXT], float (*sH)[TY + 1][TX + 1],
+                                          const CoefTile<TY, CZ>& ct, int lz, int cur, int k,
+                                          const PlaneIn& in, float eo[3], float& hx_prev, float& hy_prev, double& e2,
+                                          float wave) {
+    const int nxt = 1 - cur;
+    const int N = c.N, P = c.P, x = c.x, y = c.y, row = c.row, lane = c.lane;
+    const int ok = k * c.plane;
+    const int szk = P > 0 ? slab_coord(k, g.nz, P) : -1;
+    int poH[3], poE[3];
+    psi_offsets(g, c.own, k, c.live ? szk : -1, 0, poH);
+    psi_offsets(g, c.own, k, c.live ? szk : -1, 1, poE);
+    if (!c.live) poH[0] = poH[1] = poE[0] = poE[1] = -1;
+    float ph[6], phh[6], pe[6];
+    #pragma unroll
+    for (int t = 0; t < 6; ++t) { ph[t] = in.ph[t]; phh[t] = in.phh[t]; pe[t] = in.pe[t]; }
+    // ---- E^n of plane k+1 into LDS ----
+    #pragma unroll
+    for (int q = 0; q < 3; ++q) sE[nxt][q][row + 1][lane + 1] = in.e1[q];
+    if (c.rlx >= 0) {
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) sE[nxt][q][c.rly][c.rlx] = in.er[q];
+    }
+    __syncthreads();
+    // ---- first half: H^{n+1/2} on the own cell and the halo cell ----
+    float h[3];
+    {
+        float t[6];
+        h_terms<TY>(sE[cur], sE[nxt], lane + 1, row + 1, t);
+        h_update_cf(g.dt, cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, lz), t, in.h0, ph, h);
+        if (!c.live) h[0] = h[1] = h[2] = 0.0f;
+    }
+    const int idx = c.live ? c.own.xy + ok : -1;
+    bst3(b.H1, idx, N, h);
+    bst_psi(g, b.psiH1, poH, ph);
+    if constexpr (REC >= 0) {
+        // interface shell of a kept step: H^{n+1/2} on the low faces, E^n on the high faces;
+        // a cell lies on at most one face
+        const bool jI = y >= P && y < g.ny - P, kI = k >= P && k < g.nz - P, iI = x >= P && x < g.nx - P;
+        int blk = 0, o = 0;
+        float v0 = 0.0f, v1 = 0.0f;
+        bool on = c.live;
+        if (x == P - 1 && jI && kI) { blk = 0; o = (k - P) * g.my + (y - P); v0 = h[1]; v1 = h[2]; }
+        else if (y == P - 1 && iI && kI) { blk = 2; o = (k - P) * g.mx + (x - P); v0 = h[2]; v1 = h[0]; }
+        else if (k == P - 1 && iI && jI) { blk = 4; o = (y - P) * g.mx + (x - P); v0 = h[0]; v1 = h[1]; }
+        else if (x == g.nx - P && jI && kI) { blk = 6; o = (k - P) * g.my + (y - P); v0 = eo[1]; v1 = eo[2]; }
+        else if (y == g.ny - P && iI && kI) { blk = 8; o = (k - P) * g.mx + (x - P); v0 = eo[2]; v1 = eo[0]; }
+        else if (k == g.nz - P && iI && jI) { blk = 10; o = (y - P) * g.mx + (x - P); v0 = eo[0]; v1 = eo[1]; }
+        else on = false;
+        record_b<REC>(b.store, b.staging, block_offset(g, blk) + o, on, v0);
+        record_b<REC>(b.store, b.staging, block_offset(g, blk + 1) + o, on, v1);
+    }
+    sH[0][row + 1][lane + 1] = h[0];
+    sH[1][row + 1][lane + 1] = h[1];
+    sH[2][row + 1][lane + 1] = h[2];
+    if (c.hex >= 0) {
+        float hh[3] = {0.0f, 0.0f, 0.0f};
+        if (c.hc.xy >= 0) {
+            float t[6];
+            h_terms<TY>(sE[cur], sE[nxt], c.hex, c.hey, t);
+            h_update_cf(g.dt, cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, lz), t, in.hh0, phh, hh);
+        }
+        sH[0][c.hey][c.hex] = hh[0];
+        sH[1][c.hey][c.hex] = hh[1];
+        sH[2][c.hey][c.hex] = hh[2];
+    }
+    __syncthreads();
+    // ---- second half: E^{n+1} on the own cell ----
+    float t[6];
+    t[0] = h[2] - sH[2][row][lane + 1];       // (Ex, y, +, Hz)
+    t[1] = h[1] - hy_prev;                    // (Ex, z, -, Hy)
+    t[2] = h[0] - hx_prev;                    // (Ey, z, +, Hx)
+    t[3] = h[2] - sH[2][row + 1][lane];       // (Ey, x, -, Hz)
+    t[4] = h[1] - sH[1][row + 1][lane];       // (Ez, x, +, Hy)
+    t[5] = h[0] - sH[0][row][lane + 1];       // (Ez, y, -, Hx)
+    cpml_apply(cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, lz), t, pe);
+    bst_psi(g, b.psiE, poE, pe);
+    float u[3] = {t[0] - t[1], t[2] - t[3], t[4] - t[5]};
+    const float jv = wave * in.sp;   // 0 outside the source box
+    u[0] -= g.src_comp == 0 ? jv : 0.0f;
+    u[1] -= g.src_comp == 1 ? jv : 0.0f;
+    u[2] -= g.src_comp == 2 ? jv : 0.0f;
+    const float cc = g.dt / in.ep;
+    float e[3];
+    e[0] = eo[0] + cc * u[0];
+    e[1] = eo[1] + cc * u[1];
+    e[2] = eo[2] + cc * u[2];
+    bst3(b.E1, idx, N, e);
+    if (c.live && in_box(x, y, k, g.det_lo, g.det_hi))
+        e2 += (double)e[0] * e[0] + (double)e[1] * e[1] + (double)e[2] * e[2];
+    hx_prev = h[0];
+    hy_prev = h[1];
+    eo[0] = in.e1[0]; eo[1] = in.e1[1]; eo[2] = in.e1[2];
 }
 
 // One full forward step n: (E^n, H^{n-1/2}) in E0/H0 -> (E^{n+1}, H^{n+1/2}) in E1/H1.
 // H-side PML auxiliaries ping-pong (psiH0 -> psiH1); E-side ones are updated in place.
-template <int TY>
-__global__ __launch_bounds__(TX * TY) void k_fwd_step(Grid g, Tiling tl, const float* __restrict__ E0,
+// The z-march over CZ planes is unrolled and software-pipelined: the loads of plane
+// k+1 are issued before the stores of plane k into the other of two register sets,
+// so no wait for them also waits for those stores (loads and stores retire in order).
+template <int TY, int REC, int CZ>
+#ifndef FDTD_FWD_WAVES
+#define FDTD_FWD_WAVES 1
+#endif
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FWD_WAVES))) void k_fwd_step(Grid g, Tiling tl, const float* __restrict__ E0,
                                                       const float* __restrict__ H0, float* __restrict__ E1,
                                                       float* __restrict__ H1, const float* __restrict__ psiH0,
                                                       float* __restrict__ psiH1, float* __restrict__ psiE,
@@ -111,161 +235,108 @@ __global__ __launch_bounds__(TX * TY) void k_fwd_step(Grid g, Tiling tl, const f
                                                       float* __restrict__ staging, int slice) {
     __shared__ float sE[2][3][TY + 2][EXT];
     __shared__ float sH[3][TY + 1][TX + 1];
+    __shared__ CoefTile<TY, CZ> ct;
     __shared__ double red[TY];
     const int L = logical_tile(tl.count);
     const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
-    const int i0 = tix * TX, j0 = tiy * TY, k0 = tiz * tl.cz;
-    const int k1 = min(k0 + tl.cz, g.nz);
-    const int lane = threadIdx.x, row = threadIdx.y;
-    const int tid = row * TX + lane;
-    const int x = i0 + lane, y = j0 + row;
-    const bool live = x < g.nx && y < g.ny;
-    const int N = (int)g.N;
-    const int P = g.P;
+    FwdCtx<TY> c;
+    c.i0 = tix * TX;
+    c.j0 = tiy * TY;
+    const int k0 = tiz * CZ;
+    const int k1 = min(k0 + CZ, g.nz);
+    c.lane = threadIdx.x;
+    c.row = threadIdx.y;
+    c.tid = c.row * TX + c.lane;
+    c.x = c.i0 + c.lane;
+    c.y = c.j0 + c.row;
+    c.live = c.x < g.nx && c.y < g.ny;
+    c.N = (int)g.N;
+    c.P = g.P;
+    c.plane = g.nx * g.ny;
+    const int N = c.N, P = c.P, plane = c.plane, lane = c.lane, row = c.row;
+    FwdBufs b;
+    const uint32_t fbytes = (uint32_t)(3 * N) * 4u, psib = (uint32_t)g.psi_total * 4u;
+    b.E0 = make_rsrc(E0, fbytes);
+    b.H0 = make_rsrc(H0, fbytes);
+    b.E1 = make_rsrc(E1, fbytes);
+    b.H1 = make_rsrc(H1, fbytes);
+    b.eps = make_rsrc(eps, (uint32_t)N * 4u);
+    b.psiH0 = make_rsrc(psiH0, psib);
+    b.psiH1 = make_rsrc(psiH1, psib);
+    b.psiE = make_rsrc(psiE, psib);
+    // the kept step's slice of the store (a store can exceed 4 GiB; one slice cannot)
+    b.store = make_rsrc(store ? (char*)store + (long long)slice * g.slice_stride : nullptr,
+                        store ? (uint32_t)g.slice_stride : 0u);
+    b.staging = make_rsrc(staging, g.dtype == 3 ? (uint32_t)g.vps * 4u : 0u);
+    b.src = make_rsrc(g.src_profile, (uint32_t)((g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1]) *
+                                                (g.src_hi[2] - g.src_lo[2])) * 4u);
 
-    // halo cell of the first half assigned to this thread: the row below the tile (y = j0-1)
-    // for tid < TX, the column left of it (x = i0-1) for TX <= tid < TX + TY
-    int hex = -1, hey = -1, hxg = -1, hyg = -1;
-    if (tid < TX + TY) {
-        if (tid < TX) { hex = tid + 1; hey = 0; } else { hex = 0; hey = tid - TX + 1; }
-        const int xr = i0 - 1 + hex, yr = j0 - 1 + hey;
-        if (xr < g.nx && yr < g.ny) {
-            hxg = bound(xr, g.nx, g.periodic);
-            hyg = bound(yr, g.ny, g.periodic);
-        }
+    // columns this thread touches: its own, one position of the LDS ring, one halo H cell
+    c.own = make_col(g, c.x, c.y);
+    c.rlx = c.rly = -1;
+    c.ring.xy = -1;
+    if (row == 0) { c.rlx = lane + 1; c.rly = 0; c.ring = make_col(g, c.i0 + lane, c.j0 - 1); }
+    else if (row == 1) { c.rlx = lane + 1; c.rly = TY + 1; c.ring = make_col(g, c.i0 + lane, c.j0 + TY); }
+    else if (row == 2 && lane < TY + 2) { c.rlx = 0; c.rly = lane; c.ring = make_col(g, c.i0 - 1, c.j0 - 1 + lane); }
+    else if (row == 3 && lane < TY + 2) { c.rlx = EXT - 1; c.rly = lane; c.ring = make_col(g, c.i0 + TX, c.j0 - 1 + lane); }
+    c.hex = c.hey = -1;
+    c.hc.xy = -1;
+    c.hc.sx = c.hc.sy = -1;
+    if (c.tid < TX + TY) {
+        if (c.tid < TX) { c.hex = c.tid + 1; c.hey = 0; } else { c.hex = 0; c.hey = c.tid - TX + 1; }
+        const int xr = c.i0 - 1 + c.hex, yr = c.j0 - 1 + c.hey;
+        if (xr < g.nx && yr < g.ny) c.hc = make_col(g, xr, yr);   // positions past the far edge are never read
     }
 
-    // prologue: H^{n+1/2} of this column at k0 - 1 (the owner below computes the same value)
-    load_ext_plane<TY>(sE[0], E0, N, g, i0, j0, k0 - 1);
-    load_ext_plane<TY>(sE[1], E0, N, g, i0, j0, k0);
-    __syncthreads();
-    float hx_prev = 0.0f, hy_prev = 0.0f;
+    fill_coef_tile<TY, CZ>(g, ct, c.i0, c.j0, k0, c.tid, TX * TY);   // published by the prologue's barrier
+    // prologue: E^n planes k0-1 and k0 into LDS, H^{n+1/2} of this column at k0-1, and
+    // the inputs of plane k0
+    PlaneIn pin[2];
+    float eo[3];                       // E^n of the own cell on the current plane
+    float hx_prev, hy_prev;            // H^{n+1/2} of the own cell on the previous plane
     {
-        const int zb = bound(k0 - 1, g.nz, g.periodic);
-        if (live && zb >= 0) {
-            float a, b, c;
-            h_cell<TY>(g, sE[0], sE[1], lane + 1, row + 1, x, y, zb, H0, psiH0, nullptr, a, b, c);
-            hx_prev = a;
-            hy_prev = b;
+        const int zm = bound(k0 - 1, g.nz, g.periodic);
+        const int om = zm < 0 ? -1 : zm * plane;
+        const int szm = (zm >= 0 && P > 0) ? slab_coord(zm, g.nz, P) : -1;
+        float a[3], ra[3], rb[3], h0[3], p[6];
+        bld3(b.E0, (c.own.xy < 0 || om < 0) ? -1 : c.own.xy + om, N, a);
+        bld3(b.E0, c.own.xy < 0 ? -1 : c.own.xy + k0 * plane, N, eo);
+        bld3(b.E0, (c.ring.xy < 0 || om < 0) ? -1 : c.ring.xy + om, N, ra);
+        bld3(b.E0, c.ring.xy < 0 ? -1 : c.ring.xy + k0 * plane, N, rb);
+        const bool pro = c.live && zm >= 0;
+        bld3(b.H0, pro ? c.own.xy + om : -1, N, h0);
+        int po[3];
+        psi_offsets(g, c.own, zm, pro ? szm : -1, 0, po);
+        if (!pro) po[0] = po[1] = -1;
+        bld_psi(g, b.psiH0, po, p);
+        load_plane_in<TY>(g, b, c, k0, pin[0]);
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            sE[0][q][row + 1][lane + 1] = a[q];
+            sE[1][q][row + 1][lane + 1] = eo[q];
         }
+        if (c.rlx >= 0) {
+            #pragma unroll
+            for (int q = 0; q < 3; ++q) { sE[0][q][c.rly][c.rlx] = ra[q]; sE[1][q][c.rly][c.rlx] = rb[q]; }
+        }
+        __syncthreads();
+        float t[6], h[3];
+        h_terms<TY>(sE[0], sE[1], lane + 1, row + 1, t);
+        h_update_cf(g.dt, cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), t, h0, p, h);
+        hx_prev = pro ? h[0] : 0.0f;
+        hy_prev = pro ? h[1] : 0.0f;
     }
-    int cur = 1;
+    __syncthreads();   // the first plane overwrites sE[0], which the prologue has just read
     double e2 = 0.0;
-    const bool rec = slice >= 0 && P > 0;
-    const long long bs = (long long)slice * g.slice_stride;
-    for (int k = k0; k < k1; ++k) {
-        const int nxt = 1 - cur;
-        __syncthreads();                                   // sE[nxt] and sH are free
-        load_ext_plane<TY>(sE[nxt], E0, N, g, i0, j0, k + 1);
-        __syncthreads();
-        float hx = 0.0f, hy = 0.0f, hz = 0.0f;
-        const int idx = x + g.nx * (y + g.ny * k);
-        // pass 0: this thread's own cell; pass 1: its halo cell (if any).  One code path for
-        // both keeps a recomputed halo value bitwise equal to the owner's.
-        #pragma unroll 1
-        for (int pass = 0; pass < 2; ++pass) {
-            const bool own = pass == 0;
-            const bool active = own ? live : (hxg >= 0 && hyg >= 0);
-            const int cex = own ? lane + 1 : hex, cey = own ? row + 1 : hey;
-            const int cx = own ? x : hxg, cy = own ? y : hyg;
-            if (!own && hex < 0) break;
-            float a = 0.0f, b = 0.0f, c = 0.0f;
-            if (active)
-                h_cell<TY>(g, sE[cur], sE[nxt], cex, cey, cx, cy, k, H0, psiH0, own ? psiH1 : nullptr, a, b, c);
-            sH[0][cey][cex] = a;
-            sH[1][cey][cex] = b;
-            sH[2][cey][cex] = c;
-            if (own) { hx = a; hy = b; hz = c; }
-        }
-        if (live) {
-            H1[idx] = hx;
-            H1[N + idx] = hy;
-            H1[2 * N + idx] = hz;
-            if (rec) {
-                // interface shell of a kept step: H^{n+1/2} on the low faces, E^n on the high faces
-                const float exo = sE[cur][0][row + 1][lane + 1];
-                const float eyo = sE[cur][1][row + 1][lane + 1];
-                const float ezo = sE[cur][2][row + 1][lane + 1];
-                const bool jI = y >= P && y < g.ny - P, kI = k >= P && k < g.nz - P, iI = x >= P && x < g.nx - P;
-                auto put = [&](int b, int off, float v) {
-                    const long long o = block_offset(g, b) + off;
-                    if (g.dtype == 3) staging[o] = v; else store_code(store, bs, o, g.dtype, v);
-                };
-                if (x == P - 1 && jI && kI) { const int o = (k - P) * g.my + (y - P); put(0, o, hy); put(1, o, hz); }
-                if (y == P - 1 && iI && kI) { const int o = (k - P) * g.mx + (x - P); put(2, o, hz); put(3, o, hx); }
-                if (k == P - 1 && iI && jI) { const int o = (y - P) * g.mx + (x - P); put(4, o, hx); put(5, o, hy); }
-                if (x == g.nx - P && jI && kI) { const int o = (k - P) * g.my + (y - P); put(6, o, eyo); put(7, o, ezo); }
-                if (y == g.ny - P && iI && kI) { const int o = (k - P) * g.mx + (x - P); put(8, o, ezo); put(9, o, exo); }
-                if (k == g.nz - P && iI && jI) { const int o = (y - P) * g.mx + (x - P); put(10, o, exo); put(11, o, eyo); }
-            }
-        }
-        __syncthreads();
-        if (live) {
-            float t0 = hz - sH[2][row][lane + 1];       // (Ex, y, +, Hz)
-            float t1 = hy - hy_prev;                    // (Ex, z, -, Hy)
-            float t2 = hx - hx_prev;                    // (Ey, z, +, Hx)
-            float t3 = hz - sH[2][row + 1][lane];       // (Ey, x, -, Hz)
-            float t4 = hy - sH[1][row + 1][lane];       // (Ez, x, +, Hy)
-            float t5 = hx - sH[0][row][lane + 1];       // (Ez, y, -, Hx)
-            if (P > 0) {
-                const float* bE = g.coef;
-                const float* aE = g.coef + 2 * P;
-                const float* kE = g.coef + 4 * P;
-                int s = slab_coord(x, g.nx, P);
-                if (s >= 0) {
-                    const int o = (int)(g.psi_off[0] + 2 * g.slab[0]) + s + 2 * P * (y + g.ny * k);
-                    const int sl = (int)g.slab[0];
-                    const float b = bE[s], a = aE[s], kv = kE[s];
-                    const float p3 = b * psiE[o] + a * t3;
-                    const float p4 = b * psiE[o + sl] + a * t4;
-                    psiE[o] = p3;
-                    psiE[o + sl] = p4;
-                    t3 = kv * t3 + p3;
-                    t4 = kv * t4 + p4;
-                }
-                s = slab_coord(y, g.ny, P);
-                if (s >= 0) {
-                    const int o = (int)(g.psi_off[1] + 2 * g.slab[1]) + x + g.nx * (s + 2 * P * k);
-                    const int sl = (int)g.slab[1];
-                    const float b = bE[s], a = aE[s], kv = kE[s];
-                    const float p0 = b * psiE[o] + a * t0;
-                    const float p5 = b * psiE[o + sl] + a * t5;
-                    psiE[o] = p0;
-                    psiE[o + sl] = p5;
-                    t0 = kv * t0 + p0;
-                    t5 = kv * t5 + p5;
-                }
-                s = slab_coord(k, g.nz, P);
-                if (s >= 0) {
-                    const int o = (int)(g.psi_off[2] + 2 * g.slab[2]) + x + g.nx * (y + g.ny * s);
-                    const int sl = (int)g.slab[2];
-                    const float b = bE[s], a = aE[s], kv = kE[s];
-                    const float p1 = b * psiE[o] + a * t1;
-                    const float p2 = b * psiE[o + sl] + a * t2;
-                    psiE[o] = p1;
-                    psiE[o + sl] = p2;
-                    t1 = kv * t1 + p1;
-                    t2 = kv * t2 + p2;
-                }
-            }
-            float ux = t0 - t1, uy = t2 - t3, uz = t4 - t5;
-            if (in_box(x, y, k, g.src_lo, g.src_hi)) {
-                const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
-                const float jv = wave * g.src_profile[(x - g.src_lo[0]) + sxn * ((y - g.src_lo[1]) + syn * (k - g.src_lo[2]))];
-                if (g.src_comp == 0) ux -= jv; else if (g.src_comp == 1) uy -= jv; else uz -= jv;
-            }
-            const float c = g.dt / eps[idx];
-            const float ex = sE[cur][0][row + 1][lane + 1] + c * ux;
-            const float ey = sE[cur][1][row + 1][lane + 1] + c * uy;
-            const float ez = sE[cur][2][row + 1][lane + 1] + c * uz;
-            E1[idx] = ex;
-            E1[N + idx] = ey;
-            E1[2 * N + idx] = ez;
-            if (in_box(x, y, k, g.det_lo, g.det_hi)) e2 += (double)ex * ex + (double)ey * ey + (double)ez * ez;
-        }
-        hx_prev = hx;
-        hy_prev = hy;
-        cur = nxt;
+    // REC: the storage type of this kept step, or -1 on a step that records nothing
+    #pragma unroll
+    for (int kk = 0; kk < CZ; ++kk) {
+        const int k = k0 + kk;
+        if (kk + 1 < CZ)   // inputs of the next plane (an unused valid plane past the end of the grid)
+            load_plane_in<TY>(g, b, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+        if (k < k1)
+            fwd_plane<TY, REC, CZ>(g, b, c, sE, sH, ct, kk + 1, (kk + 1) & 1, k, pin[kk & 1], eo, hx_prev, hy_prev, e2,
+                                   wave);
     }
     // detector partial of this tile (tiles intersecting the detector only; uniform per block)
     const int dx = tix - tl.dtx0, dy = tiy - tl.dty0, dz = tiz - tl.dtz0;
@@ -273,7 +344,7 @@ __global__ __launch_bounds__(TX * TY) void k_fwd_step(Grid g, Tiling tl, const f
     for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off, 64);
     if (lane == 0) red[row] = e2;
     __syncthreads();
-    if (tid == 0) {
+    if (c.tid == 0) {
         double sum = 0.0;
         for (int w = 0; w < TY; ++w) sum += red[w];
         partials[dx + (long long)tl.dntx * (dy + (long long)tl.dnty * dz)] = sum;
@@ -326,15 +397,33 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
     if (threadIdx.x == 0) *loss = red[0];
 }
 
+template <int TY, int CZ>
+static void launch_fwd_step_t(const Grid& g, const Tiling& t, const float* E0, const float* H0, float* E1, float* H1,
+                              const float* psiH0, float* psiH1, float* psiE, const float* eps, float wave,
+                              double* partials, void* store, float* staging, int slice, hipStream_t s) {
+    const dim3 grid(t.count), block(TX, TY);
+    if (slice < 0 || g.P == 0) {
+        launch_kernel(K_FWD_STEP, k_fwd_step<TY, -1, CZ>, grid, block, s, g, t, E0, H0, E1, H1, psiH0, psiH1, psiE,
+                      eps, wave, partials, store, staging, slice);
+        return;
+    }
+    with_dtype(g.dtype, [&]<int DT>() {
+        launch_kernel(K_FWD_STEP, k_fwd_step<TY, DT, CZ>, grid, block, s, g, t, E0, H0, E1, H1, psiH0, psiH1, psiE,
+                      eps, wave, partials, store, staging, slice);
+    });
+}
+
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* E0, const float* H0, float* E1, float* H1,
                      const float* psiH0, float* psiH1, float* psiE, const float* eps, float wave, double* partials,
                      void* store, float* staging, int slice, hipStream_t s) {
-    if (t.ty == 8)
-        launch_kernel(K_FWD_STEP, k_fwd_step<8>, dim3(t.count), dim3(TX, 8), s, g, t, E0, H0, E1, H1, psiH0, psiH1,
-                      psiE, eps, wave, partials, store, staging, slice);
+    if (t.ty == 4 && t.cz == 4)
+        launch_fwd_step_t<4, 4>(g, t, E0, H0, E1, H1, psiH0, psiH1, psiE, eps, wave, partials, store, staging, slice, s);
+    else if (t.ty == 4)
+        launch_fwd_step_t<4, 8>(g, t, E0, H0, E1, H1, psiH0, psiH1, psiE, eps, wave, partials, store, staging, slice, s);
+    else if (t.cz == 4)
+        launch_fwd_step_t<8, 4>(g, t, E0, H0, E1, H1, psiH0, psiH1, psiE, eps, wave, partials, store, staging, slice, s);
     else
-        launch_kernel(K_FWD_STEP, k_fwd_step<4>, dim3(t.count), dim3(TX, 4), s, g, t, E0, H0, E1, H1, psiH0, psiH1,
-                      psiE, eps, wave, partials, store, staging, slice);
+        launch_fwd_step_t<8, 8>(g, t, E0, H0, E1, H1, psiH0, psiH1, psiE, eps, wave, partials, store, staging, slice, s);
 }
 
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s) {

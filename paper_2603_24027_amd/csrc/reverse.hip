@@ -38,236 +38,275 @@ namespace fdtd {
 // adjoint sweep
 // --------------------------------------------------------------------------
 
-// gbar of the six E-half terms at (x, y, z) from v = (dt/eps) Ebar_eff.
-// Terms: 0 (vx,+,y) 1 (vx,-,z) 2 (vy,+,z) 3 (vy,-,x) 4 (vz,+,x) 5 (vz,-,y).
-__device__ inline void gbar_e(const Grid& g, int x, int y, int z, float vx, float vy, float vz,
-                              const float* __restrict__ psi_in, float* __restrict__ psi_out, float o[6]) {
-    o[0] = vx; o[1] = -vx; o[2] = vy; o[3] = -vy; o[4] = vz; o[5] = -vz;
-    const int P = g.P;
-    if (P == 0) return;
-    const float* b = g.coef;
-    const float* a = g.coef + 2 * P;
-    const float* kv = g.coef + 4 * P;
-    int s = slab_coord(x, g.nx, P);
-    if (s >= 0) {
-        const int sl = (int)g.slab[0];
-        const int q = (int)(g.psi_off[0] + 2 * g.slab[0]) + s + 2 * P * (y + g.ny * z);
-        const float pa = psi_in[q] + o[3], pb = psi_in[q + sl] + o[4];
-        o[3] = kv[s] * o[3] + a[s] * pa;
-        o[4] = kv[s] * o[4] + a[s] * pb;
-        if (psi_out) { psi_out[q] = b[s] * pa; psi_out[q + sl] = b[s] * pb; }
-    }
-    s = slab_coord(y, g.ny, P);
-    if (s >= 0) {
-        const int sl = (int)g.slab[1];
-        const int q = (int)(g.psi_off[1] + 2 * g.slab[1]) + x + g.nx * (s + 2 * P * z);
-        const float pa = psi_in[q] + o[0], pb = psi_in[q + sl] + o[5];
-        o[0] = kv[s] * o[0] + a[s] * pa;
-        o[5] = kv[s] * o[5] + a[s] * pb;
-        if (psi_out) { psi_out[q] = b[s] * pa; psi_out[q + sl] = b[s] * pb; }
-    }
-    s = slab_coord(z, g.nz, P);
-    if (s >= 0) {
-        const int sl = (int)g.slab[2];
-        const int q = (int)(g.psi_off[2] + 2 * g.slab[2]) + x + g.nx * (y + g.ny * s);
-        const float pa = psi_in[q] + o[1], pb = psi_in[q + sl] + o[2];
-        o[1] = kv[s] * o[1] + a[s] * pa;
-        o[2] = kv[s] * o[2] + a[s] * pb;
-        if (psi_out) { psi_out[q] = b[s] * pa; psi_out[q + sl] = b[s] * pb; }
-    }
-}
-
-// gbar of the six H-half terms at (x, y, z) from w = -dt Hbar_new.
-// Terms: 0 (wx,+,y) 1 (wx,-,z) 2 (wy,+,z) 3 (wy,-,x) 4 (wz,+,x) 5 (wz,-,y).
-__device__ inline void gbar_h(const Grid& g, int x, int y, int z, float wx, float wy, float wz,
-                              const float* __restrict__ psi_in, float* __restrict__ psi_out, float o[6]) {
-    o[0] = wx; o[1] = -wx; o[2] = wy; o[3] = -wy; o[4] = wz; o[5] = -wz;
-    const int P = g.P;
-    if (P == 0) return;
-    const float* b = g.coef + 6 * P;
-    const float* a = g.coef + 8 * P;
-    const float* kv = g.coef + 10 * P;
-    int s = slab_coord(x, g.nx, P);
-    if (s >= 0) {
-        const int sl = (int)g.slab[0];
-        const int q = (int)g.psi_off[0] + s + 2 * P * (y + g.ny * z);
-        const float pa = psi_in[q] + o[3], pb = psi_in[q + sl] + o[4];
-        o[3] = kv[s] * o[3] + a[s] * pa;
-        o[4] = kv[s] * o[4] + a[s] * pb;
-        if (psi_out) { psi_out[q] = b[s] * pa; psi_out[q + sl] = b[s] * pb; }
-    }
-    s = slab_coord(y, g.ny, P);
-    if (s >= 0) {
-        const int sl = (int)g.slab[1];
-        const int q = (int)g.psi_off[1] + x + g.nx * (s + 2 * P * z);
-        const float pa = psi_in[q] + o[0], pb = psi_in[q + sl] + o[5];
-        o[0] = kv[s] * o[0] + a[s] * pa;
-        o[5] = kv[s] * o[5] + a[s] * pb;
-        if (psi_out) { psi_out[q] = b[s] * pa; psi_out[q + sl] = b[s] * pb; }
-    }
-    s = slab_coord(z, g.nz, P);
-    if (s >= 0) {
-        const int sl = (int)g.slab[2];
-        const int q = (int)g.psi_off[2] + x + g.nx * (y + g.ny * s);
-        const float pa = psi_in[q] + o[1], pb = psi_in[q + sl] + o[2];
-        o[1] = kv[s] * o[1] + a[s] * pa;
-        o[2] = kv[s] * o[2] + a[s] * pb;
-        if (psi_out) { psi_out[q] = b[s] * pa; psi_out[q + sl] = b[s] * pb; }
-    }
-}
-
-// E-half gbar of one extended-plane position (ex, ey) at plane z into sG[t][ey][ex];
-// returns Ebar_eff there.  Positions outside the domain (zero boundary) give 0.
-template <int TY>
-__device__ inline void ge_position(const Grid& g, float (*sG)[TY + 2][EXT], int ex, int ey, int xr, int yr, int z,
-                                   const float* __restrict__ Eb0, const float* __restrict__ Es,
-                                   const float* __restrict__ eps, const float* __restrict__ psi_in,
-                                   float* __restrict__ psi_out, float eb[3]) {
-    const int x = bound(xr, g.nx, g.periodic), y = bound(yr, g.ny, g.periodic), zb = bound(z, g.nz, g.periodic);
-    float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    eb[0] = eb[1] = eb[2] = 0.0f;
-    if ((x | y | zb) >= 0) {
-        const int N = (int)g.N;
-        const int idx = x + g.nx * (y + g.ny * zb);
-        eb[0] = Eb0[idx];
-        eb[1] = Eb0[N + idx];
-        eb[2] = Eb0[2 * N + idx];
-        if (in_box(x, y, zb, g.det_lo, g.det_hi)) {       // this step's loss seed 2 E^{n+1}
-            eb[0] += 2.0f * Es[idx];
-            eb[1] += 2.0f * Es[N + idx];
-            eb[2] += 2.0f * Es[2 * N + idx];
-        }
-        const float c = g.dt / eps[idx];
-        gbar_e(g, x, y, zb, c * eb[0], c * eb[1], c * eb[2], psi_in, psi_out, o);
-    }
-    #pragma unroll
-    for (int t = 0; t < 6; ++t) sG[t][ey][ex] = o[t];
-}
-
-// E-half gbar on the extended plane z (tile plus a one-cell ring); the owner
-// of a tile cell writes its PML auxiliaries when `owned`.  Returns the own
-// cell's Ebar_eff.
-template <int TY>
-__device__ inline void ge_plane(const Grid& g, float (*sG)[TY + 2][EXT], int i0, int j0, int z, bool owned,
-                                const float* Eb0, const float* Es, const float* eps, const float* psi_in,
-                                float* psi_out, float eb[3]) {
-    const int lane = threadIdx.x, ty = threadIdx.y;
-    const bool live = i0 + lane < g.nx && j0 + ty < g.ny;
-    ge_position<TY>(g, sG, lane + 1, ty + 1, i0 + lane, j0 + ty, z, Eb0, Es, eps, psi_in,
-                    (owned && live) ? psi_out : nullptr, eb);
-    float dummy[3];
-    if (ty == 0)
-        ge_position<TY>(g, sG, lane + 1, 0, i0 + lane, j0 - 1, z, Eb0, Es, eps, psi_in, nullptr, dummy);
-    else if (ty == 1)
-        ge_position<TY>(g, sG, lane + 1, TY + 1, i0 + lane, j0 + TY, z, Eb0, Es, eps, psi_in, nullptr, dummy);
-    else if (ty == 2 && lane < TY + 2)
-        ge_position<TY>(g, sG, 0, lane, i0 - 1, j0 - 1 + lane, z, Eb0, Es, eps, psi_in, nullptr, dummy);
-    else if (ty == 3 && lane < TY + 2)
-        ge_position<TY>(g, sG, EXT - 1, lane, i0 + TX, j0 - 1 + lane, z, Eb0, Es, eps, psi_in, nullptr, dummy);
+// Transpose of one half step's CPML at one cell.  o holds the six raw terms
+// (s * v_c for the E half, s * w_c for the H half; x: 3, 4; y: 0, 5; z: 1, 2);
+// inside the slab of a term's axis P = psibar + o, o <- kinv o + a P and the new
+// auxiliary is b P.  Outside a slab the coefficients (0, 0, 1) leave o unchanged.
+__device__ inline void gbar_apply(const Cf& cx, const Cf& cy, const Cf& cz, float o[6], const float pin[6],
+                                  float pout[6]) {
+    float q;
+    q = pin[3] + o[3]; o[3] = cx.k * o[3] + cx.a * q; pout[3] = cx.b * q;
+    q = pin[4] + o[4]; o[4] = cx.k * o[4] + cx.a * q; pout[4] = cx.b * q;
+    q = pin[0] + o[0]; o[0] = cy.k * o[0] + cy.a * q; pout[0] = cy.b * q;
+    q = pin[5] + o[5]; o[5] = cy.k * o[5] + cy.a * q; pout[5] = cy.b * q;
+    q = pin[1] + o[1]; o[1] = cz.k * o[1] + cz.a * q; pout[1] = cz.b * q;
+    q = pin[2] + o[2]; o[2] = cz.k * o[2] + cz.a * q; pout[2] = cz.b * q;
 }
 
 // Hbar after the E-half transpose at the cell of extended coordinates (ex, ey):
 // Hbar0 + sum_t (gbar_t(p) - gbar_t(p + e_d)), +z from the next plane.
 template <int TY>
 __device__ inline void hbar_new(const float (*cur)[TY + 2][EXT], const float (*nxt)[TY + 2][EXT], int ex, int ey,
-                                float h0x, float h0y, float h0z, float& hx, float& hy, float& hz) {
-    hx = h0x + (cur[2][ey][ex] - nxt[2][ey][ex]) + (cur[5][ey][ex] - cur[5][ey + 1][ex]);
-    hy = h0y + (cur[1][ey][ex] - nxt[1][ey][ex]) + (cur[4][ey][ex] - cur[4][ey][ex + 1]);
-    hz = h0z + (cur[0][ey][ex] - cur[0][ey + 1][ex]) + (cur[3][ey][ex] - cur[3][ey][ex + 1]);
+                                const float h0[3], float h[3]) {
+    h[0] = h0[0] + (cur[2][ey][ex] - nxt[2][ey][ex]) + (cur[5][ey][ex] - cur[5][ey + 1][ex]);
+    h[1] = h0[1] + (cur[1][ey][ex] - nxt[1][ey][ex]) + (cur[4][ey][ex] - cur[4][ey][ex + 1]);
+    h[2] = h0[2] + (cur[0][ey][ex] - cur[0][ey + 1][ex]) + (cur[3][ey][ex] - cur[3][ey][ex + 1]);
+}
+
+struct AdjBufs {
+    rsrc_t Eb0, Hb0, Eb1, Hb1, eps, pin, pout;
+};
+
+// What the adjoint sweep reads from memory for plane k of its column, loaded
+// one plane ahead: Ebar (loss seed included), eps and the E-side auxiliaries at
+// plane k+1 for the own cell and the LDS-ring position; Hbar and the H-side
+// auxiliaries at plane k for the own cell and the halo cell.
+struct AdjIn {
+    float eb[3], ep, pe[6];
+    float rb[3], rep, rpe[6];
+    float hb[3], ph[6];
+    float hhb[3], phh[6];
+};
+
+// Ebar, eps and E-side auxiliaries of column c on plane z (z < 0: outside, all 0, eps 1).
+__device__ __forceinline__ void load_ge_in(const Grid& g, const AdjBufs& b, const Col& c, int z, int plane,
+                                           float eb[3], float& ep, float pe[6]) {
+    const int idx = (c.xy < 0 || z < 0) ? -1 : c.xy + z * plane;
+    bld3(b.Eb0, idx, (int)g.N, eb);
+    const float e = bld(b.eps, idx < 0 ? OOB : (uint32_t)idx << 2);
+    ep = idx < 0 ? 1.0f : e;
+    int po[3];
+    psi_offsets(g, c, z, (idx >= 0 && g.P > 0) ? slab_coord(z, g.nz, g.P) : -1, 1, po);
+    if (idx < 0) po[0] = po[1] = po[2] = -1;
+    bld_psi(g, b.pin, po, pe);
 }
 
 template <int TY>
-__global__ __launch_bounds__(TX * TY) void k_adj_step(Grid g, Tiling tl, const float* __restrict__ Eb0,
-                                                      const float* __restrict__ Hb0, float* __restrict__ Eb1,
-                                                      float* __restrict__ Hb1, const float* __restrict__ Es,
-                                                      const float* __restrict__ eps, const float* __restrict__ psi_in,
-                                                      float* __restrict__ psi_out) {
+__device__ __forceinline__ void load_adj_in(const Grid& g, const AdjBufs& b, const FwdCtx<TY>& c, int k, AdjIn& d) {
+    const int z1 = bound(k + 1, g.nz, g.periodic);
+    load_ge_in(g, b, c.own, z1, c.plane, d.eb, d.ep, d.pe);
+    load_ge_in(g, b, c.ring, z1, c.plane, d.rb, d.rep, d.rpe);
+    const int ok = k * c.plane;
+    const int szk = g.P > 0 ? slab_coord(k, g.nz, g.P) : -1;
+    bld3(b.Hb0, c.live ? c.own.xy + ok : -1, c.N, d.hb);
+    bld3(b.Hb0, c.hc.xy >= 0 ? c.hc.xy + ok : -1, c.N, d.hhb);
+    int po[3];
+    psi_offsets(g, c.own, k, c.live ? szk : -1, 0, po);
+    if (!c.live) po[0] = po[1] = -1;
+    bld_psi(g, b.pin, po, d.ph);
+    psi_offsets(g, c.hc, k, szk, 0, po);
+    bld_psi(g, b.pin, po, d.phh);
+}
+
+// E-half gbar at one position from its inputs: v = (dt/eps) Ebar, raw terms
+// (vx, -vx, vy, -vy, vz, -vz), CPML transpose; the new auxiliaries go to pout.
+__device__ __forceinline__ void ge_terms(float dt, const float eb[3], float ep, const float pe[6], const Cf& cx,
+                                         const Cf& cy, const Cf& cz, float o[6], float pout[6]) {
+    const float cc = dt / ep;
+    const float vx = cc * eb[0], vy = cc * eb[1], vz = cc * eb[2];
+    o[0] = vx; o[1] = -vx; o[2] = vy; o[3] = -vy; o[4] = vz; o[5] = -vz;
+    gbar_apply(cx, cy, cz, o, pe, pout);
+}
+
+// One plane k of the adjoint sweep: E-half gbar of plane k+1 (own cell and ring
+// position) into LDS, the H-half transpose on the own and halo cells of plane k,
+// then Ebar of the own cell at plane k.
+template <int TY, int CZ>
+__device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const FwdCtx<TY>& c,
+                                          float (*sG)[6][TY + 2][EXT], float (*sGH)[TY + 1][TX + 1],
+                                          const CoefTile<TY, CZ>& ct, int kk, int k, bool own_next, int cur,
+                                          const AdjIn& in, float ebc[3], float& g1p, float& g2p) {
+    const int nxt = 1 - cur;
+    const int N = c.N, row = c.row, lane = c.lane;
+    const float dt = g.dt;
+    const int z1 = bound(k + 1, g.nz, g.periodic);
+    // ---- E-half gbar of plane k+1 ----
+    {
+        float o[6], po[6];
+        ge_terms(dt, in.eb, in.ep, in.pe, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, kk + 2), o, po);
+        #pragma unroll
+        for (int t = 0; t < 6; ++t) sG[nxt][t][row + 1][lane + 1] = o[t];
+        int off[3];
+        const bool w = c.live && own_next && z1 >= 0;
+        psi_offsets(g, c.own, z1, (w && g.P > 0) ? slab_coord(z1, g.nz, g.P) : -1, 1, off);
+        if (!w) off[0] = off[1] = off[2] = -1;
+        bst_psi(g, b.pout, off, po);
+        if (c.rlx >= 0) {
+            ge_terms(dt, in.rb, in.rep, in.rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, kk + 2), o, po);
+            #pragma unroll
+            for (int t = 0; t < 6; ++t) sG[nxt][t][c.rly][c.rlx] = o[t];
+        }
+    }
+    __syncthreads();
+    // ---- H-half transpose at plane k: own cell (stored) and halo cell (LDS only) ----
+    const int ok = k * c.plane;
+    const int szk = g.P > 0 ? slab_coord(k, g.nz, g.P) : -1;
+    const int idx = c.live ? c.own.xy + ok : -1;
+    float og[6];
+    {
+        float h[3], po[6];
+        hbar_new<TY>(sG[cur], sG[nxt], lane + 1, row + 1, in.hb, h);
+        bst3(b.Hb1, idx, N, h);
+        og[0] = -dt * h[0]; og[1] = dt * h[0]; og[2] = -dt * h[1]; og[3] = dt * h[1]; og[4] = -dt * h[2];
+        og[5] = dt * h[2];
+        gbar_apply(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, kk + 1), og, in.ph, po);
+        if (!c.live) og[0] = og[1] = og[2] = og[3] = og[4] = og[5] = 0.0f;
+        int off[3];
+        psi_offsets(g, c.own, k, c.live ? szk : -1, 0, off);
+        if (!c.live) off[0] = off[1] = -1;
+        bst_psi(g, b.pout, off, po);
+        #pragma unroll
+        for (int t = 0; t < 6; ++t) sGH[t][row + 1][lane + 1] = og[t];
+    }
+    if (c.hex >= 0) {
+        float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (c.hc.xy >= 0) {
+            float h[3], po[6];
+            hbar_new<TY>(sG[cur], sG[nxt], c.hex, c.hey, in.hhb, h);
+            o[0] = -dt * h[0]; o[1] = dt * h[0]; o[2] = -dt * h[1]; o[3] = dt * h[1]; o[4] = -dt * h[2];
+            o[5] = dt * h[2];
+            gbar_apply(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, kk + 1), o, in.phh, po);
+        }
+        #pragma unroll
+        for (int t = 0; t < 6; ++t) sGH[t][c.hey][c.hex] = o[t];
+    }
+    __syncthreads();
+    // ---- Ebar at plane k: Ex <- terms 2 (z), 5 (y); Ey <- 1 (z), 4 (x); Ez <- 0 (y), 3 (x) ----
+    float e[3];
+    e[0] = ebc[0] + (g2p - og[2]) + (sGH[5][row][lane + 1] - og[5]);
+    e[1] = ebc[1] + (g1p - og[1]) + (sGH[4][row + 1][lane] - og[4]);
+    e[2] = ebc[2] + (sGH[0][row][lane + 1] - og[0]) + (sGH[3][row + 1][lane] - og[3]);
+    bst3(b.Eb1, idx, N, e);
+    g1p = og[1];
+    g2p = og[2];
+    ebc[0] = in.eb[0]; ebc[1] = in.eb[1]; ebc[2] = in.eb[2];
+}
+
+// One adjoint step: (Ebar, Hbar, psibar) in Eb0/Hb0/psi_in -> Eb1/Hb1/psi_out.
+// Ebar already carries this step's loss seed (added by the primal reversal).
+// Unrolled over the CZ planes and software-pipelined like the forward sweep.
+#ifndef FDTD_ADJ_WAVES
+#define FDTD_ADJ_WAVES 1
+#endif
+template <int TY, int CZ>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_ADJ_WAVES))) void k_adj_step(
+    Grid g, Tiling tl, const float* __restrict__ Eb0, const float* __restrict__ Hb0, float* __restrict__ Eb1,
+    float* __restrict__ Hb1, const float* __restrict__ eps, const float* __restrict__ psi_in,
+    float* __restrict__ psi_out) {
     __shared__ float sG[2][6][TY + 2][EXT];
     __shared__ float sGH[6][TY + 1][TX + 1];
+    __shared__ CoefTile<TY, CZ> ct;
     const int L = logical_tile(tl.count);
     const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
-    const int i0 = tix * TX, j0 = tiy * TY, k0 = tiz * tl.cz;
-    const int k1 = min(k0 + tl.cz, g.nz);
-    const int lane = threadIdx.x, row = threadIdx.y;
-    const int tid = row * TX + lane;
-    const int x = i0 + lane, y = j0 + row;
-    const bool live = x < g.nx && y < g.ny;
-    const int N = (int)g.N;
+    FwdCtx<TY> c;
+    c.i0 = tix * TX;
+    c.j0 = tiy * TY;
+    const int k0 = tiz * CZ;
+    const int k1 = min(k0 + CZ, g.nz);
+    c.lane = threadIdx.x;
+    c.row = threadIdx.y;
+    c.tid = c.row * TX + c.lane;
+    c.x = c.i0 + c.lane;
+    c.y = c.j0 + c.row;
+    c.live = c.x < g.nx && c.y < g.ny;
+    c.N = (int)g.N;
+    c.P = g.P;
+    c.plane = g.nx * g.ny;
+    const int lane = c.lane, row = c.row;
     const float dt = g.dt;
+    AdjBufs b;
+    const uint32_t fbytes = (uint32_t)(3 * c.N) * 4u, psib = (uint32_t)g.psi_total * 4u;
+    b.Eb0 = make_rsrc(Eb0, fbytes);
+    b.Hb0 = make_rsrc(Hb0, fbytes);
+    b.Eb1 = make_rsrc(Eb1, fbytes);
+    b.Hb1 = make_rsrc(Hb1, fbytes);
+    b.eps = make_rsrc(eps, (uint32_t)c.N * 4u);
+    b.pin = make_rsrc(psi_in, psib);
+    b.pout = make_rsrc(psi_out, psib);
 
-    // halo cell of the first half (as in the forward step): row y = j0-1 or column x = i0-1
-    int hex = -1, hey = -1, hxg = -1, hyg = -1;
-    if (tid < TX + TY) {
-        if (tid < TX) { hex = tid + 1; hey = 0; } else { hex = 0; hey = tid - TX + 1; }
-        const int xr = i0 - 1 + hex, yr = j0 - 1 + hey;
-        if (xr < g.nx && yr < g.ny) {
-            hxg = bound(xr, g.nx, g.periodic);
-            hyg = bound(yr, g.ny, g.periodic);
-        }
+    c.own = make_col(g, c.x, c.y);
+    c.rlx = c.rly = -1;
+    c.ring.xy = -1;
+    c.ring.sx = c.ring.sy = -1;
+    if (row == 0) { c.rlx = lane + 1; c.rly = 0; c.ring = make_col(g, c.i0 + lane, c.j0 - 1); }
+    else if (row == 1) { c.rlx = lane + 1; c.rly = TY + 1; c.ring = make_col(g, c.i0 + lane, c.j0 + TY); }
+    else if (row == 2 && lane < TY + 2) { c.rlx = 0; c.rly = lane; c.ring = make_col(g, c.i0 - 1, c.j0 - 1 + lane); }
+    else if (row == 3 && lane < TY + 2) { c.rlx = EXT - 1; c.rly = lane; c.ring = make_col(g, c.i0 + TX, c.j0 - 1 + lane); }
+    c.hex = c.hey = -1;
+    c.hc.xy = -1;
+    c.hc.sx = c.hc.sy = -1;
+    if (c.tid < TX + TY) {
+        if (c.tid < TX) { c.hex = c.tid + 1; c.hey = 0; } else { c.hex = 0; c.hey = c.tid - TX + 1; }
+        const int xr = c.i0 - 1 + c.hex, yr = c.j0 - 1 + c.hey;
+        if (xr < g.nx && yr < g.ny) c.hc = make_col(g, xr, yr);
     }
+    fill_coef_tile<TY, CZ>(g, ct, c.i0, c.j0, k0, c.tid, TX * TY);   // published by the prologue's barrier
 
-    float ebc[3], ebn[3];
-    ge_plane<TY>(g, sG[0], i0, j0, k0 - 1, false, Eb0, Es, eps, psi_in, psi_out, ebn);
-    ge_plane<TY>(g, sG[1], i0, j0, k0, true, Eb0, Es, eps, psi_in, psi_out, ebc);
-    __syncthreads();
-    // H-half gbar of this column at k0 - 1 (terms along z), from Hbar after the E half there
-    float g1p = 0.0f, g2p = 0.0f;
+    // prologue: E-half gbar of planes k0-1 and k0, Ebar of the own cell at k0, and the
+    // z-terms of the H-half gbar of the own cell at k0-1
+    AdjIn pin[2];
+    float ebc[3];
+    float g1p, g2p;
     {
-        const int zb = bound(k0 - 1, g.nz, g.periodic);
-        if (live && zb >= 0) {
-            const int idx = x + g.nx * (y + g.ny * zb);
-            float hx, hy, hz, o[6];
-            hbar_new<TY>(sG[0], sG[1], lane + 1, row + 1, Hb0[idx], Hb0[N + idx], Hb0[2 * N + idx], hx, hy, hz);
-            gbar_h(g, x, y, zb, -dt * hx, -dt * hy, -dt * hz, psi_in, nullptr, o);
-            g1p = o[1];
-            g2p = o[2];
-        }
-    }
-    int cur = 1;
-    for (int k = k0; k < k1; ++k) {
-        const int nxt = 1 - cur;
-        __syncthreads();
-        ge_plane<TY>(g, sG[nxt], i0, j0, k + 1, k + 1 < k1, Eb0, Es, eps, psi_in, psi_out, ebn);
-        __syncthreads();
-        float og[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        #pragma unroll 1
-        for (int pass = 0; pass < 2; ++pass) {
-            const bool own = pass == 0;
-            if (!own && hex < 0) break;
-            const bool active = own ? live : (hxg >= 0 && hyg >= 0);
-            const int cex = own ? lane + 1 : hex, cey = own ? row + 1 : hey;
-            const int cx = own ? x : hxg, cy = own ? y : hyg;
-            float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            if (active) {
-                const int idx = cx + g.nx * (cy + g.ny * k);
-                float hx, hy, hz;
-                hbar_new<TY>(sG[cur], sG[nxt], cex, cey, Hb0[idx], Hb0[N + idx], Hb0[2 * N + idx], hx, hy, hz);
-                if (own) {
-                    Hb1[idx] = hx;
-                    Hb1[N + idx] = hy;
-                    Hb1[2 * N + idx] = hz;
-                }
-                gbar_h(g, cx, cy, k, -dt * hx, -dt * hy, -dt * hz, psi_in, own ? psi_out : nullptr, o);
-            }
+        const int zm = bound(k0 - 1, g.nz, g.periodic);
+        const int z0 = bound(k0, g.nz, g.periodic);
+        float eb[3], ep, pe[6], rb[3], rep, rpe[6], eb0[3], ep0, pe0[6], rb0[3], rep0, rpe0[6], hb[3], ph[6];
+        load_ge_in(g, b, c.own, zm, c.plane, eb, ep, pe);
+        load_ge_in(g, b, c.ring, zm, c.plane, rb, rep, rpe);
+        load_ge_in(g, b, c.own, z0, c.plane, eb0, ep0, pe0);
+        load_ge_in(g, b, c.ring, z0, c.plane, rb0, rep0, rpe0);
+        const bool pro = c.live && zm >= 0;
+        bld3(b.Hb0, pro ? c.own.xy + zm * c.plane : -1, c.N, hb);
+        int off[3];
+        psi_offsets(g, c.own, zm, (pro && g.P > 0) ? slab_coord(zm, g.nz, g.P) : -1, 0, off);
+        if (!pro) off[0] = off[1] = -1;
+        bld_psi(g, b.pin, off, ph);
+        load_adj_in<TY>(g, b, c, k0, pin[0]);
+        float o[6], po[6];
+        ge_terms(dt, eb, ep, pe, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, 0), o, po);
+        #pragma unroll
+        for (int t = 0; t < 6; ++t) sG[0][t][row + 1][lane + 1] = o[t];
+        ge_terms(dt, eb0, ep0, pe0, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, 1), o, po);
+        #pragma unroll
+        for (int t = 0; t < 6; ++t) sG[1][t][row + 1][lane + 1] = o[t];
+        // the own cell's E-side auxiliaries at k0 belong to this block
+        psi_offsets(g, c.own, z0, (c.live && g.P > 0) ? slab_coord(z0, g.nz, g.P) : -1, 1, off);
+        if (!c.live) off[0] = off[1] = off[2] = -1;
+        bst_psi(g, b.pout, off, po);
+        if (c.rlx >= 0) {
+            ge_terms(dt, rb, rep, rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, 0), o, po);
             #pragma unroll
-            for (int t = 0; t < 6; ++t) sGH[t][cey][cex] = o[t];
-            if (own) {
-                #pragma unroll
-                for (int t = 0; t < 6; ++t) og[t] = o[t];
-            }
+            for (int t = 0; t < 6; ++t) sG[0][t][c.rly][c.rlx] = o[t];
+            ge_terms(dt, rb0, rep0, rpe0, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, 1), o, po);
+            #pragma unroll
+            for (int t = 0; t < 6; ++t) sG[1][t][c.rly][c.rlx] = o[t];
         }
+        ebc[0] = eb0[0]; ebc[1] = eb0[1]; ebc[2] = eb0[2];
         __syncthreads();
-        if (live) {
-            const int idx = x + g.nx * (y + g.ny * k);
-            // Ex <- terms 2 (z), 5 (y); Ey <- 1 (z), 4 (x); Ez <- 0 (y), 3 (x)
-            Eb1[idx] = ebc[0] + (g2p - og[2]) + (sGH[5][row][lane + 1] - og[5]);
-            Eb1[N + idx] = ebc[1] + (g1p - og[1]) + (sGH[4][row + 1][lane] - og[4]);
-            Eb1[2 * N + idx] = ebc[2] + (sGH[0][row][lane + 1] - og[0]) + (sGH[3][row + 1][lane] - og[3]);
-        }
-        g1p = og[1];
-        g2p = og[2];
-        ebc[0] = ebn[0]; ebc[1] = ebn[1]; ebc[2] = ebn[2];
-        cur = nxt;
+        float h[3];
+        hbar_new<TY>(sG[0], sG[1], lane + 1, row + 1, hb, h);
+        o[0] = -dt * h[0]; o[1] = dt * h[0]; o[2] = -dt * h[1]; o[3] = dt * h[1]; o[4] = -dt * h[2]; o[5] = dt * h[2];
+        gbar_apply(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), o, ph, po);
+        g1p = pro ? o[1] : 0.0f;
+        g2p = pro ? o[2] : 0.0f;
+    }
+    __syncthreads();   // the first plane overwrites sG[0], which the prologue has just read
+    #pragma unroll
+    for (int kk = 0; kk < CZ; ++kk) {
+        const int k = k0 + kk;
+        if (kk + 1 < CZ) load_adj_in<TY>(g, b, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+        if (k < k1)
+            adj_plane<TY, CZ>(g, b, c, sG, sGH, ct, kk, k, k + 1 < k1, (kk + 1) & 1, pin[kk & 1], ebc, g1p, g2p);
     }
 }
 
@@ -280,182 +319,278 @@ struct Box {            // the region prim_rev sweeps: I plus a one-cell shell
     int n[3];           // extent
 };
 
-// E^n at one position of plane z (global x, y) from the LDS planes of
-// H^{n+1/2} at z (hc) and z - 1 (hp), extended-plane coordinates (ex, ey).
-// Interior cells are reversed; high-face shell cells take the recorded values;
-// anything else is unused and set to 0.  Also returns U - J for the gradient.
+struct RevBufs {
+    rsrc_t E0, H0, E1, H1, eps, src;
+};
+
+// What the primal reversal reads for plane k, loaded one plane ahead: H^{n+1/2}
+// at plane k+1 (own cell and LDS-ring position), and E^{n+1}, eps and the source
+// profile at plane k+1 (own cell and the extra +x / +y position).
+struct RevIn {
+    float h[3], rh[3], e[3], xe[3], ep, xep, sp, xsp;
+};
+
 template <int TY>
-__device__ __forceinline__ void e_rev_position(const Grid& g, const float (*hc)[TY + 2][EXT], const float (*hp)[TY + 2][EXT],
-                                      int ex, int ey, int x, int y, int z, const float* __restrict__ E0,
-                                      const float* __restrict__ eps, const void* __restrict__ store,
-                                      const Interp& qE, float wave, float e[3], float uj[3], bool& interior) {
-    const int P = g.P;
-    e[0] = e[1] = e[2] = 0.0f;
-    uj[0] = uj[1] = uj[2] = 0.0f;
-    interior = false;
-    // positions past the edge wrap (periodic grid) or are zero
-    x = bound(x, g.nx, g.periodic);
-    y = bound(y, g.ny, g.periodic);
-    z = bound(z, g.nz, g.periodic);
-    if ((x | y | z) < 0) return;
+struct RevCtx {
+    int i0, j0, lane, row, x, y, N, plane;
+    bool live;
+    Col own, ring, xcol;
+    int rlx, rly, pex, pey;
+};
+
+__device__ __forceinline__ uint32_t src_off(const Grid& g, const Col& c, int z) {
+    if (c.xy < 0 || z < 0) return OOB;
+    if (!in_box(c.x, c.y, z, g.src_lo, g.src_hi)) return OOB;
+    const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
+    return (uint32_t)((c.x - g.src_lo[0]) + sxn * ((c.y - g.src_lo[1]) + syn * (z - g.src_lo[2]))) << 2;
+}
+
+// E^{n+1}, eps and source profile of column c on plane z (z < 0 or outside: 0, eps 1)
+__device__ __forceinline__ void load_e_in(const Grid& g, const RevBufs& b, const Col& c, int z, int plane,
+                                          float e[3], float& ep, float& sp) {
+    const int idx = (c.xy < 0 || z < 0) ? -1 : c.xy + z * plane;
+    bld3(b.E0, idx, (int)g.N, e);
+    const float v = bld(b.eps, idx < 0 ? OOB : (uint32_t)idx << 2);
+    ep = idx < 0 ? 1.0f : v;
+    sp = bld(b.src, src_off(g, c, z));
+}
+
+template <int TY>
+__device__ __forceinline__ void load_rev_in(const Grid& g, const RevBufs& b, const RevCtx<TY>& c, int k, RevIn& d) {
+    const int z1 = bound(k + 1, g.nz, g.periodic);
+    bld3(b.H0, (c.own.xy < 0 || z1 < 0) ? -1 : c.own.xy + z1 * c.plane, c.N, d.h);
+    bld3(b.H0, (c.ring.xy < 0 || z1 < 0) ? -1 : c.ring.xy + z1 * c.plane, c.N, d.rh);
+    load_e_in(g, b, c.own, z1, c.plane, d.e, d.ep, d.sp);
+    load_e_in(g, b, c.xcol, z1, c.plane, d.xe, d.xep, d.xsp);
+}
+
+// E^n at one position of plane z (column col, wrapped; extended-plane coordinates
+// (ex, ey) of the LDS H planes at z (hc) and z-1 (hp)).  Interior cells are
+// reversed, E^n = E^{n+1} - (dt/eps)(curl H - J); high-face shell cells take the
+// recorded values; anything else is 0.  u returns curl H - J (interior cells).
+template <int TY, int DT>
+__device__ __forceinline__ void e_rev(const Grid& g, const float (*hc)[TY + 2][EXT], const float (*hp)[TY + 2][EXT],
+                                      int ex, int ey, const Col& col, int z, const float e1[3], float ep, float sp,
+                                      float wave, const void* __restrict__ store, const Interp& qE, float e[3],
+                                      float u[3], bool& interior) {
+    const int P = g.P, x = col.x, y = col.y;
+    const bool inside = col.xy >= 0 && z >= 0;
     const bool iI = x >= P && x < g.nx - P, jI = y >= P && y < g.ny - P, kI = z >= P && z < g.nz - P;
-    if (iI && jI && kI) {
-        interior = true;
-        const int N = (int)g.N;
-        const int idx = x + g.nx * (y + g.ny * z);
-        const float hx = hc[0][ey][ex], hy = hc[1][ey][ex], hz = hc[2][ey][ex];
-        float ux = (hz - hc[2][ey - 1][ex]) - (hy - hp[1][ey][ex]);
-        float uy = (hx - hp[0][ey][ex]) - (hz - hc[2][ey][ex - 1]);
-        float uz = (hy - hc[1][ey][ex - 1]) - (hx - hc[0][ey - 1][ex]);
-        if (in_box(x, y, z, g.src_lo, g.src_hi)) {
-            const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
-            const float jv = wave * g.src_profile[(x - g.src_lo[0]) + sxn * ((y - g.src_lo[1]) + syn * (z - g.src_lo[2]))];
-            if (g.src_comp == 0) ux -= jv; else if (g.src_comp == 1) uy -= jv; else uz -= jv;
+    interior = inside && iI && jI && kI;
+    const float hx = hc[0][ey][ex], hy = hc[1][ey][ex], hz = hc[2][ey][ex];
+    u[0] = (hz - hc[2][ey - 1][ex]) - (hy - hp[1][ey][ex]);
+    u[1] = (hx - hp[0][ey][ex]) - (hz - hc[2][ey][ex - 1]);
+    u[2] = (hy - hc[1][ey][ex - 1]) - (hx - hc[0][ey - 1][ex]);
+    const float jv = wave * sp;   // 0 outside the source box
+    u[0] -= g.src_comp == 0 ? jv : 0.0f;
+    u[1] -= g.src_comp == 1 ? jv : 0.0f;
+    u[2] -= g.src_comp == 2 ? jv : 0.0f;
+    const float cc = g.dt / ep;
+    e[0] = interior ? e1[0] - cc * u[0] : 0.0f;
+    e[1] = interior ? e1[1] - cc * u[1] : 0.0f;
+    e[2] = interior ? e1[2] - cc * u[2] : 0.0f;
+    if (P > 0 && inside && !interior) {     // high-face interface shell (rare)
+        if (x == g.nx - P && jI && kI) {
+            const int o = (z - P) * g.my + (y - P);
+            e[1] = shell_value_t<DT>(g, store, qE, 6, o);
+            e[2] = shell_value_t<DT>(g, store, qE, 7, o);
+        } else if (y == g.ny - P && iI && kI) {
+            const int o = (z - P) * g.mx + (x - P);
+            e[2] = shell_value_t<DT>(g, store, qE, 8, o);
+            e[0] = shell_value_t<DT>(g, store, qE, 9, o);
+        } else if (z == g.nz - P && iI && jI) {
+            const int o = (y - P) * g.mx + (x - P);
+            e[0] = shell_value_t<DT>(g, store, qE, 10, o);
+            e[1] = shell_value_t<DT>(g, store, qE, 11, o);
         }
-        const float c = g.dt / eps[idx];
-        e[0] = E0[idx] - c * ux;
-        e[1] = E0[N + idx] - c * uy;
-        e[2] = E0[2 * N + idx] - c * uz;
-        uj[0] = ux; uj[1] = uy; uj[2] = uz;
-        return;
-    }
-    if (P == 0) return;
-    if (x == g.nx - P && jI && kI) {
-        const int o = (z - P) * g.my + (y - P);
-        e[1] = shell_value(g, store, qE, 6, o);
-        e[2] = shell_value(g, store, qE, 7, o);
-    } else if (y == g.ny - P && iI && kI) {
-        const int o = (z - P) * g.mx + (x - P);
-        e[2] = shell_value(g, store, qE, 8, o);
-        e[0] = shell_value(g, store, qE, 9, o);
-    } else if (z == g.nz - P && iI && jI) {
-        const int o = (y - P) * g.mx + (x - P);
-        e[0] = shell_value(g, store, qE, 10, o);
-        e[1] = shell_value(g, store, qE, 11, o);
     }
 }
 
-// E^n at sE position (ex, ey) of plane z (global x = i0 + ex, y = j0 + ey) into sE[.][ey][ex];
-// the owning block also writes it and accumulates the gradient there.
-template <int TY>
-__device__ __forceinline__ void e_pos(const Grid& g, float (*sE)[TY + 1][TX + 1], const float (*hc)[TY + 2][EXT],
-                                      const float (*hp)[TY + 2][EXT], int i0, int j0, int z, int ex, int ey,
-                                      bool owner, const float* __restrict__ E0, float* __restrict__ E1,
-                                      const float* __restrict__ eps, const float* __restrict__ Eb0,
-                                      const void* __restrict__ store, const Interp& qE, float wave,
-                                      double* __restrict__ grad) {
-    float e[3], uj[3];
+// The owner of an interior cell on the design or detector box: this step's loss
+// seed 2 E^{n+1} is added to Ebar in place (the adjoint sweep reads it seeded),
+// and the gradient epsbar -= (dt/eps^2) Ebar . (U - J) accumulates in FP64.
+__device__ __forceinline__ void grad_and_seed(const Grid& g, float* __restrict__ Eb0, double* __restrict__ grad,
+                                              int x, int y, int z, int idx, const float e1[3], float ep,
+                                              const float u[3]) {
+    const bool det = in_box(x, y, z, g.det_lo, g.det_hi), des = in_box(x, y, z, g.des_lo, g.des_hi);
+    if (!det && !des) return;
+    const int N = (int)g.N;
+    float eb[3] = {Eb0[idx], Eb0[N + idx], Eb0[2 * N + idx]};
+    if (det) {
+        eb[0] += 2.0f * e1[0];
+        eb[1] += 2.0f * e1[1];
+        eb[2] += 2.0f * e1[2];
+        Eb0[idx] = eb[0];
+        Eb0[N + idx] = eb[1];
+        Eb0[2 * N + idx] = eb[2];
+    }
+    if (des) {
+        const int dx = g.des_hi[0] - g.des_lo[0], dy = g.des_hi[1] - g.des_lo[1];
+        const int di = (x - g.des_lo[0]) + dx * ((y - g.des_lo[1]) + dy * (z - g.des_lo[2]));
+        const double ee = (double)ep;
+        const double s = (double)eb[0] * u[0] + (double)eb[1] * u[1] + (double)eb[2] * u[2];
+        grad[di] -= (double)g.dt / (ee * ee) * s;
+    }
+}
+
+// E^n of plane z on the own cell (written by its owner, with gradient and seed) and the
+// extra position, into the LDS plane sE.
+template <int TY, int DT>
+__device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const RevCtx<TY>& c,
+                                        float (*sE)[TY + 1][TX + 1], const float (*hc)[TY + 2][EXT],
+                                        const float (*hp)[TY + 2][EXT], int z, bool owned, const float e1[3], float ep,
+                                        float sp, const float xe1[3], float xep, float xsp, float wave,
+                                        const void* __restrict__ store, const Interp& qE, float* __restrict__ Eb0,
+                                        double* __restrict__ grad) {
+    const int lane = c.lane, row = c.row;
+    float e[3], u[3];
     bool interior;
-    const int xg = i0 + ex, yg = j0 + ey;
-    e_rev_position<TY>(g, hc, hp, ex + 1, ey + 1, xg, yg, z, E0, eps, store, qE, wave, e, uj, interior);
-    sE[0][ey][ex] = e[0];
-    sE[1][ey][ex] = e[1];
-    sE[2][ey][ex] = e[2];
-    if (owner && interior) {
-        const int N = (int)g.N;
-        const int idx = xg + g.nx * (yg + g.ny * z);
-        E1[idx] = e[0];
-        E1[N + idx] = e[1];
-        E1[2 * N + idx] = e[2];
-        if (in_box(xg, yg, z, g.des_lo, g.des_hi)) {
-            float ebx = Eb0[idx], eby = Eb0[N + idx], ebz = Eb0[2 * N + idx];
-            if (in_box(xg, yg, z, g.det_lo, g.det_hi)) {          // this step's loss seed 2 E^{n+1}
-                ebx += 2.0f * E0[idx];
-                eby += 2.0f * E0[N + idx];
-                ebz += 2.0f * E0[2 * N + idx];
-            }
-            const int dx = g.des_hi[0] - g.des_lo[0], dy = g.des_hi[1] - g.des_lo[1];
-            const int di = (xg - g.des_lo[0]) + dx * ((yg - g.des_lo[1]) + dy * (z - g.des_lo[2]));
-            const double ee = (double)eps[idx];
-            const double s = (double)ebx * uj[0] + (double)eby * uj[1] + (double)ebz * uj[2];
-            grad[di] -= (double)g.dt / (ee * ee) * s;
-        }
+    e_rev<TY, DT>(g, hc, hp, lane + 1, row + 1, c.own, z, e1, ep, sp, wave, store, qE, e, u, interior);
+    sE[0][row][lane] = e[0];
+    sE[1][row][lane] = e[1];
+    sE[2][row][lane] = e[2];
+    const bool w = owned && c.live && interior;
+    const int idx = w ? c.own.xy + z * c.plane : -1;
+    bst3(b.E1, idx, c.N, e);
+    if (w) grad_and_seed(g, Eb0, grad, c.own.x, c.own.y, z, idx, e1, ep, u);
+    if (c.pex >= 0) {
+        e_rev<TY, DT>(g, hc, hp, c.pex + 1, c.pey + 1, c.xcol, z, xe1, xep, xsp, wave, store, qE, e, u, interior);
+        sE[0][c.pey][c.pex] = e[0];
+        sE[1][c.pey][c.pex] = e[1];
+        sE[2][c.pey][c.pex] = e[2];
     }
 }
 
-template <int TY>
-__global__ __launch_bounds__(TX * TY) void k_prim_rev(Grid g, Tiling tl, Box bx, const float* __restrict__ E0,
-                                                      const float* __restrict__ H0, float* __restrict__ E1,
-                                                      float* __restrict__ H1, const float* __restrict__ eps,
-                                                      const float* __restrict__ Eb0, const void* __restrict__ store,
-                                                      Interp qE, Interp qH, int inject_h, float wave,
-                                                      double* __restrict__ grad) {
+// One reverse primal step over the box: (E^{n+1}, H^{n+1/2}) in E0/H0 -> (E^n, H^{n-1/2})
+// in E1/H1 on the interior, the shell values from the store, gradient and loss seed.
+#ifndef FDTD_REV_WAVES
+#define FDTD_REV_WAVES 1
+#endif
+template <int TY, int DT, int CZ>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_REV_WAVES))) void k_prim_rev(
+    Grid g, Tiling tl, Box bx, const float* __restrict__ E0, const float* __restrict__ H0, float* __restrict__ E1,
+    float* __restrict__ H1, const float* __restrict__ eps, float* __restrict__ Eb0, const void* __restrict__ store,
+    Interp qE, Interp qH, int inject_h, float wave, double* __restrict__ grad) {
     __shared__ float sH[2][3][TY + 2][EXT];       // H^{n+1/2}, extended planes
     __shared__ float sE[2][3][TY + 1][TX + 1];     // E^n on the tile plus the +x column / +y row
     const int L = logical_tile(tl.count);
     const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
-    const int i0 = bx.o[0] + tix * TX, j0 = bx.o[1] + tiy * TY, k0 = bx.o[2] + tiz * tl.cz;
-    const int k1 = min(k0 + tl.cz, bx.o[2] + bx.n[2]);
-    const int lane = threadIdx.x, row = threadIdx.y;
-    const int tid = row * TX + lane;
-    const int x = i0 + lane, y = j0 + row;
-    const bool live = x < bx.o[0] + bx.n[0] && y < bx.o[1] + bx.n[1];
-    const int N = (int)g.N;
-    const int P = g.P;
+    RevCtx<TY> c;
+    c.i0 = bx.o[0] + tix * TX;
+    c.j0 = bx.o[1] + tiy * TY;
+    const int k0 = bx.o[2] + tiz * CZ;
+    const int k1 = min(k0 + CZ, bx.o[2] + bx.n[2]);
+    c.lane = threadIdx.x;
+    c.row = threadIdx.y;
+    const int lane = c.lane, row = c.row, tid = row * TX + lane;
+    c.x = c.i0 + lane;
+    c.y = c.j0 + row;
+    c.live = c.x < bx.o[0] + bx.n[0] && c.y < bx.o[1] + bx.n[1];
+    c.N = (int)g.N;
+    c.plane = g.nx * g.ny;
+    const int N = c.N, P = g.P;
     const float dt = g.dt;
+    RevBufs b;
+    const uint32_t fbytes = (uint32_t)(3 * N) * 4u;
+    b.E0 = make_rsrc(E0, fbytes);
+    b.H0 = make_rsrc(H0, fbytes);
+    b.E1 = make_rsrc(E1, fbytes);
+    b.H1 = make_rsrc(H1, fbytes);
+    b.eps = make_rsrc(eps, (uint32_t)N * 4u);
+    b.src = make_rsrc(g.src_profile, (uint32_t)((g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1]) *
+                                                (g.src_hi[2] - g.src_lo[2])) * 4u);
+    c.own = make_col(g, c.x, c.y);
+    c.rlx = c.rly = -1;
+    c.ring.xy = -1;
+    c.ring.x = c.ring.y = -1;
+    if (row == 0) { c.rlx = lane + 1; c.rly = 0; c.ring = make_col(g, c.i0 + lane, c.j0 - 1); }
+    else if (row == 1) { c.rlx = lane + 1; c.rly = TY + 1; c.ring = make_col(g, c.i0 + lane, c.j0 + TY); }
+    else if (row == 2 && lane < TY + 2) { c.rlx = 0; c.rly = lane; c.ring = make_col(g, c.i0 - 1, c.j0 - 1 + lane); }
+    else if (row == 3 && lane < TY + 2) { c.rlx = EXT - 1; c.rly = lane; c.ring = make_col(g, c.i0 + TX, c.j0 - 1 + lane); }
+    // extra E^n position: the column x = i0+TX (tid <= TY) or the row y = j0+TY
+    c.pex = c.pey = -1;
+    c.xcol.xy = -1;
+    c.xcol.x = c.xcol.y = -1;
+    if (tid < TY + 1) { c.pex = TX; c.pey = tid; }
+    else if (tid < TY + 1 + TX) { c.pex = tid - TY - 1; c.pey = TY; }
+    if (c.pex >= 0) c.xcol = make_col(g, c.i0 + c.pex, c.j0 + c.pey);
 
-    // extra E^n position of the first half: the column x = i0+TX (tid < TY+1) or the
-    // row y = j0+TY (TY+1 <= tid < TY+1+TX); (ex, ey) in the sE plane
-    int pex = -1, pey = -1;
-    if (tid < TY + 1) { pex = TX; pey = tid; }
-    else if (tid < TY + 1 + TX) { pex = tid - TY - 1; pey = TY; }
-
-    // prologue: H^{n+1/2} planes k0-1 and k0, then E^n at k0
-    load_ext_plane<TY>(sH[0], H0, N, g, i0, j0, k0 - 1);
-    load_ext_plane<TY>(sH[1], H0, N, g, i0, j0, k0);
-    __syncthreads();
-    #pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1 && pex < 0) break;
-        e_pos<TY>(g, sE[0], sH[1], sH[0], i0, j0, k0, pass ? pex : lane, pass ? pey : row, pass == 0 && live, E0, E1,
-                  eps, Eb0, store, qE, wave, grad);
+    // prologue: H^{n+1/2} planes k0-1 and k0 into LDS, then E^n at k0
+    RevIn pin[2];
+    {
+        const int zm = bound(k0 - 1, g.nz, g.periodic), z0 = bound(k0, g.nz, g.periodic);
+        float hm[3], rhm[3], h0[3], rh0[3], e1[3], xe1[3], ep, xep, sp, xsp;
+        bld3(b.H0, (c.own.xy < 0 || zm < 0) ? -1 : c.own.xy + zm * c.plane, N, hm);
+        bld3(b.H0, (c.ring.xy < 0 || zm < 0) ? -1 : c.ring.xy + zm * c.plane, N, rhm);
+        bld3(b.H0, (c.own.xy < 0 || z0 < 0) ? -1 : c.own.xy + z0 * c.plane, N, h0);
+        bld3(b.H0, (c.ring.xy < 0 || z0 < 0) ? -1 : c.ring.xy + z0 * c.plane, N, rh0);
+        load_e_in(g, b, c.own, z0, c.plane, e1, ep, sp);
+        load_e_in(g, b, c.xcol, z0, c.plane, xe1, xep, xsp);
+        load_rev_in<TY>(g, b, c, k0, pin[0]);
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            sH[0][q][row + 1][lane + 1] = hm[q];
+            sH[1][q][row + 1][lane + 1] = h0[q];
+        }
+        if (c.rlx >= 0) {
+            #pragma unroll
+            for (int q = 0; q < 3; ++q) { sH[0][q][c.rly][c.rlx] = rhm[q]; sH[1][q][c.rly][c.rlx] = rh0[q]; }
+        }
+        __syncthreads();
+        e_plane<TY, DT>(g, b, c, sE[0], sH[1], sH[0], z0, true, e1, ep, sp, xe1, xep, xsp, wave, store, qE, Eb0,
+                        grad);
     }
-    int hc = 1;      // slot of the H plane k in sH
-    int ec = 0;      // slot of the E^n plane k in sE
-    for (int k = k0; k < k1; ++k) {
-        const int hn = 1 - hc, en = 1 - ec;
-        __syncthreads();                                   // sH[hn] (plane k-1) and sE[en] are free
-        load_ext_plane<TY>(sH[hn], H0, N, g, i0, j0, k + 1);
+    __syncthreads();   // the first plane overwrites sH[0], which the prologue has just read
+    #pragma unroll
+    for (int kk = 0; kk < CZ; ++kk) {
+        const int k = k0 + kk;
+        if (kk + 1 < CZ) load_rev_in<TY>(g, b, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+        if (k >= k1) continue;
+        const int hc = (kk + 1) & 1, hn = 1 - hc;      // H plane k in sH[hc]
+        const int ec = kk & 1, en = 1 - ec;            // E^n plane k in sE[ec]
+        const RevIn& in = pin[kk & 1];
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) sH[hn][q][row + 1][lane + 1] = in.h[q];
+        if (c.rlx >= 0) {
+            #pragma unroll
+            for (int q = 0; q < 3; ++q) sH[hn][q][c.rly][c.rlx] = in.rh[q];
+        }
         __syncthreads();
         // E^n at plane k+1 (own cell, and the +x column / +y row)
-        #pragma unroll 1
-        for (int pass = 0; pass < 2; ++pass) {
-            if (pass == 1 && pex < 0) break;
-            e_pos<TY>(g, sE[en], sH[hn], sH[hc], i0, j0, k + 1, pass ? pex : lane, pass ? pey : row,
-                      pass == 0 && live && k + 1 < k1, E0, E1, eps, Eb0, store, qE, wave, grad);
-        }
+        const int z1 = bound(k + 1, g.nz, g.periodic);
+        e_plane<TY, DT>(g, b, c, sE[en], sH[hn], sH[hc], z1, k + 1 < k1, in.e, in.ep, in.sp, in.xe, in.xep, in.xsp,
+                        wave, store, qE, Eb0, grad);
         __syncthreads();
         // H^{n-1/2} at plane k on the tile
-        if (live) {
-            const bool iI = x >= P && x < g.nx - P, jI = y >= P && y < g.ny - P, kI = k >= P && k < g.nz - P;
-            const int idx = x + g.nx * (y + g.ny * k);
-            if (iI && jI && kI) {
-                const float exc = sE[ec][0][row][lane], eyc = sE[ec][1][row][lane], ezc = sE[ec][2][row][lane];
-                H1[idx] = sH[hc][0][row + 1][lane + 1] +
-                          dt * ((sE[ec][2][row + 1][lane] - ezc) - (sE[en][1][row][lane] - eyc));
-                H1[N + idx] = sH[hc][1][row + 1][lane + 1] +
-                              dt * ((sE[en][0][row][lane] - exc) - (sE[ec][2][row][lane + 1] - ezc));
-                H1[2 * N + idx] = sH[hc][2][row + 1][lane + 1] +
-                                  dt * ((sE[ec][1][row][lane + 1] - eyc) - (sE[ec][0][row + 1][lane] - exc));
-            } else if (inject_h && P > 0) {
-                // H^{n-1/2} on the low interface faces, for the next reverse step
-                if (x == P - 1 && jI && kI) {
-                    const int o = (k - P) * g.my + (y - P);
-                    H1[N + idx] = shell_value(g, store, qH, 0, o);
-                    H1[2 * N + idx] = shell_value(g, store, qH, 1, o);
-                } else if (y == P - 1 && iI && kI) {
-                    const int o = (k - P) * g.mx + (x - P);
-                    H1[2 * N + idx] = shell_value(g, store, qH, 2, o);
-                    H1[idx] = shell_value(g, store, qH, 3, o);
-                } else if (k == P - 1 && iI && jI) {
-                    const int o = (y - P) * g.mx + (x - P);
-                    H1[idx] = shell_value(g, store, qH, 4, o);
-                    H1[N + idx] = shell_value(g, store, qH, 5, o);
-                }
+        const bool iI = c.x >= P && c.x < g.nx - P, jI = c.y >= P && c.y < g.ny - P, kI = k >= P && k < g.nz - P;
+        const bool hint = c.live && iI && jI && kI;
+        const int idx = hint ? c.own.xy + k * c.plane : -1;
+        float h[3];
+        {
+            const float exc = sE[ec][0][row][lane], eyc = sE[ec][1][row][lane], ezc = sE[ec][2][row][lane];
+            h[0] = sH[hc][0][row + 1][lane + 1] + dt * ((sE[ec][2][row + 1][lane] - ezc) - (sE[en][1][row][lane] - eyc));
+            h[1] = sH[hc][1][row + 1][lane + 1] + dt * ((sE[en][0][row][lane] - exc) - (sE[ec][2][row][lane + 1] - ezc));
+            h[2] = sH[hc][2][row + 1][lane + 1] + dt * ((sE[ec][1][row][lane + 1] - eyc) - (sE[ec][0][row + 1][lane] - exc));
+        }
+        bst3(b.H1, idx, N, h);
+        if (inject_h && P > 0 && c.live && !hint) {
+            // H^{n-1/2} on the low interface faces, for the next reverse step (rare)
+            const int x = c.x, y = c.y;
+            const int gi = c.own.xy + k * c.plane;
+            if (x == P - 1 && jI && kI) {
+                const int o = (k - P) * g.my + (y - P);
+                H1[N + gi] = shell_value_t<DT>(g, store, qH, 0, o);
+                H1[2 * N + gi] = shell_value_t<DT>(g, store, qH, 1, o);
+            } else if (y == P - 1 && iI && kI) {
+                const int o = (k - P) * g.mx + (x - P);
+                H1[2 * N + gi] = shell_value_t<DT>(g, store, qH, 2, o);
+                H1[gi] = shell_value_t<DT>(g, store, qH, 3, o);
+            } else if (k == P - 1 && iI && jI) {
+                const int o = (y - P) * g.mx + (x - P);
+                H1[gi] = shell_value_t<DT>(g, store, qH, 4, o);
+                H1[N + gi] = shell_value_t<DT>(g, store, qH, 5, o);
             }
         }
-        hc = hn;
-        ec = en;
     }
 }
 
@@ -491,27 +626,44 @@ __global__ void k_scale_grad(double* g, long long n, const double* s) {
     if (i < n) g[i] *= *s;
 }
 
+template <int TY, int CZ>
+static void launch_adj_t(const Grid& g, const Tiling& t, const float* Eb0, const float* Hb0, float* Eb1, float* Hb1,
+                         const float* eps, const float* psi_in, float* psi_out, hipStream_t s) {
+    launch_kernel(K_ADJ_STEP, k_adj_step<TY, CZ>, dim3(t.count), dim3(TX, TY), s, g, t, Eb0, Hb0, Eb1, Hb1, eps,
+                  psi_in, psi_out);
+}
+
 void launch_adj_step(const Grid& g, const Tiling& t, const float* Eb0, const float* Hb0, float* Eb1, float* Hb1,
-                     const float* Es, const float* eps, const float* psi_in, float* psi_out, hipStream_t s) {
-    if (t.ty == 8)
-        launch_kernel(K_ADJ_STEP, k_adj_step<8>, dim3(t.count), dim3(TX, 8), s, g, t, Eb0, Hb0, Eb1, Hb1, Es, eps,
-                      psi_in, psi_out);
-    else
-        launch_kernel(K_ADJ_STEP, k_adj_step<4>, dim3(t.count), dim3(TX, 4), s, g, t, Eb0, Hb0, Eb1, Hb1, Es, eps,
-                      psi_in, psi_out);
+                     const float* eps, const float* psi_in, float* psi_out, hipStream_t s) {
+    if (t.ty == 4 && t.cz == 4) launch_adj_t<4, 4>(g, t, Eb0, Hb0, Eb1, Hb1, eps, psi_in, psi_out, s);
+    else if (t.ty == 4) launch_adj_t<4, 8>(g, t, Eb0, Hb0, Eb1, Hb1, eps, psi_in, psi_out, s);
+    else if (t.cz == 4) launch_adj_t<8, 4>(g, t, Eb0, Hb0, Eb1, Hb1, eps, psi_in, psi_out, s);
+    else launch_adj_t<8, 8>(g, t, Eb0, Hb0, Eb1, Hb1, eps, psi_in, psi_out, s);
+}
+
+template <int TY, int CZ>
+static void launch_prim_rev_t(const Grid& g, const Tiling& t, const Box& b, const float* E0, const float* H0,
+                              float* E1, float* H1, const float* eps, float* Eb0, const void* store, Interp qE,
+                              Interp qH, int inject_h, float wave, double* grad, hipStream_t s) {
+    with_dtype(g.dtype, [&]<int DT>() {
+        launch_kernel(K_PRIM_REV, k_prim_rev<TY, DT, CZ>, dim3(t.count), dim3(TX, TY), s, g, t, b, E0, H0, E1, H1,
+                      eps, Eb0, store, qE, qH, inject_h, wave, grad);
+    });
 }
 
 void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], const float* E0,
-                     const float* H0, float* E1, float* H1, const float* eps, const float* Eb0, const void* store,
+                     const float* H0, float* E1, float* H1, const float* eps, float* Eb0, const void* store,
                      Interp qE, Interp qH, int inject_h, float wave, double* grad, hipStream_t s) {
     Box b;
     for (int d = 0; d < 3; ++d) { b.o[d] = box_o[d]; b.n[d] = box_n[d]; }
-    if (t.ty == 8)
-        launch_kernel(K_PRIM_REV, k_prim_rev<8>, dim3(t.count), dim3(TX, 8), s, g, t, b, E0, H0, E1, H1, eps, Eb0,
-                      store, qE, qH, inject_h, wave, grad);
+    if (t.ty == 4 && t.cz == 4)
+        launch_prim_rev_t<4, 4>(g, t, b, E0, H0, E1, H1, eps, Eb0, store, qE, qH, inject_h, wave, grad, s);
+    else if (t.ty == 4)
+        launch_prim_rev_t<4, 8>(g, t, b, E0, H0, E1, H1, eps, Eb0, store, qE, qH, inject_h, wave, grad, s);
+    else if (t.cz == 4)
+        launch_prim_rev_t<8, 4>(g, t, b, E0, H0, E1, H1, eps, Eb0, store, qE, qH, inject_h, wave, grad, s);
     else
-        launch_kernel(K_PRIM_REV, k_prim_rev<4>, dim3(t.count), dim3(TX, 4), s, g, t, b, E0, H0, E1, H1, eps, Eb0,
-                      store, qE, qH, inject_h, wave, grad);
+        launch_prim_rev_t<8, 8>(g, t, b, E0, H0, E1, H1, eps, Eb0, store, qE, qH, inject_h, wave, grad, s);
 }
 
 void launch_inject_h(const Grid& g, float* H, const void* store, Interp q, hipStream_t s) {
