@@ -82,7 +82,8 @@ extern "C" {
  * Problem statement: grid with PML faces, permittivity map, source, detector
  * and Courant number (Section 2 and Eq. 1; PML from Section 1).
  *
- *   nx, ny, nz      full grid in cells, PML included (each >= 1; 12 * cells < 2^31)
+ *   nx, ny, nz      full grid in cells, PML included (each >= 1; 24 * cells < 2^31,
+ *                   and the two copies of the PML auxiliaries below 2 GiB)
  *   pml             PML thickness P on all six faces (0 <= P <= FDTD_MAX_PML,
  *                   2P < each extent); the interior I is [P, n-P) on each axis
  *   steps           T >= 1 time steps

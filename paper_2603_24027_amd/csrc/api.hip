@@ -97,9 +97,9 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     if (!p || !cfg) return fail(FDTD_EINVAL, "problem and store config must not be NULL");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(FDTD_EINVAL, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
-    // kernels address a 3-component field as one buffer with 32-bit byte offsets below 2^31
-    if (p->ny > 4 * 65535 || p->nz > 65535 || 12 * (int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
-        return fail(FDTD_EINVAL, "grid too large: 12 * cells must stay below 2^31");
+    // kernels address the six field components as one buffer with 32-bit byte offsets below 2^31
+    if (p->ny > 4 * 65535 || p->nz > 65535 || 24 * (int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
+        return fail(FDTD_EINVAL, "grid too large: 24 * cells must stay below 2^31");
     if (p->steps < 1) return fail(FDTD_EINVAL, "steps must be >= 1 (got %d)", p->steps);
     if (p->pml < 0 || p->pml > FDTD_MAX_PML) return fail(FDTD_EINVAL, "pml must be in [0, %d]", FDTD_MAX_PML);
     const int n[3] = {p->nx, p->ny, p->nz};
@@ -142,6 +142,8 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     g.psi_off[1] = 4 * g.slab[0];
     g.psi_off[2] = 4 * (g.slab[0] + g.slab[1]);
     g.psi_total = 4 * (g.slab[0] + g.slab[1] + g.slab[2]);
+    if (8 * (int64_t)g.psi_total >= ((int64_t)1 << 31))
+        return fail(FDTD_EINVAL, "PML too large: the two copies of the auxiliaries must stay below 2 GiB");
     g.src_comp = p->src_comp;
     for (int d = 0; d < 3; ++d) {
         g.src_lo[d] = p->src_lo[d]; g.src_hi[d] = p->src_hi[d];
@@ -154,13 +156,14 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     const uint64_t vbytes = (uint64_t)storage_bytes(cfg->dtype);
     const uint64_t slices = ((uint64_t)p->steps + cfg->k - 1) / cfg->k;
     g.slice_stride = (long long)align_up(vps * vbytes, 256);
+    for (int b = 0; b < 12; ++b) g.rec_off[b] = P > 0 ? (uint32_t)block_offset(g, b) : 0u;
     g.scale_off = (long long)(slices * (uint64_t)g.slice_stride);
     g.dbx0 = p->det_lo[0] / BX; g.dnbx = (p->det_hi[0] - 1) / BX - g.dbx0 + 1;
     g.dby0 = p->det_lo[1] / BY; g.dnby = (p->det_hi[1] - 1) / BY - g.dby0 + 1;
     g.dbz0 = p->det_lo[2];      g.dnbz = p->det_hi[2] - p->det_lo[2];
     Tiling& t = pl->fwd;
-    t.ty = env_int("FDTD_TILE_Y", 8) == 4 ? 4 : 8;
-    t.cz = env_int("FDTD_TILE_Z", 8) == 4 ? 4 : 8;
+    t.ty = env_int("FDTD_TILE_Y", 4) == 8 ? 8 : 4;
+    t.cz = env_int("FDTD_TILE_Z", 4) == 8 ? 8 : 4;
     t.ntx = (p->nx + TX - 1) / TX;
     t.nty = (p->ny + t.ty - 1) / t.ty;
     t.ntz = (p->nz + t.cz - 1) / t.cz;
@@ -175,6 +178,8 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     }
     Tiling& r = pl->rev;
     r = t;
+    r.ty = env_int("FDTD_REV_TILE_Y", t.ty) == 8 ? 8 : 4;
+    r.cz = env_int("FDTD_REV_TILE_Z", t.cz) == 8 ? 8 : 4;
     r.ntx = (pl->box_n[0] + TX - 1) / TX;
     r.nty = (pl->box_n[1] + r.ty - 1) / r.ty;
     r.ntz = (pl->box_n[2] + r.cz - 1) / r.cz;
@@ -400,9 +405,7 @@ int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const 
             const int slice = ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1;
             const float* in = F[(start + n) & 1];
             float* out = F[(start + n + 1) & 1];
-            const float* psiH0 = psi + (n & 1) * pl.psi_floats;
-            float* psiH1 = psi + ((n + 1) & 1) * pl.psi_floats;
-            launch_fwd_step(g, pl.fwd, in, in + 3 * N, out, out + 3 * N, psiH0, psiH1, psi, eps, wave[n],
+            launch_fwd_step(g, pl.fwd, in, out, psi, n & 1, eps, wave[n],
                             partials + (int64_t)n * pl.per_step, store, staging, slice, q);
             if (slice >= 0 && fp8) launch_rec_quant(g, staging, store, slice, q);
         }

@@ -56,6 +56,7 @@ struct Grid {
     long long vps;           // values per kept step
     long long slice_stride;  // bytes between kept steps in the store
     long long scale_off;     // byte offset of the FP8 scale table in the store
+    uint32_t rec_off[12];    // element offset of each (face, component) block within a kept step
     // detector-loss partials (forward): blocks intersecting the detector
     int dbx0, dby0, dbz0, dnbx, dnby, dnbz;
 };
@@ -323,20 +324,17 @@ __device__ inline void record_t(void* store, float* staging, long long byte_slic
 }
 
 // Record one value of a kept step through a range-checked buffer store (dropped
-// when the offset is OOB): the scaled FP8 type goes to the FP32 staging buffer,
-// every other type straight to the store.  `st` covers the kept step's slice of
-// the store, `elem` is the element index within it (block offset + position).
+// when `on` is false): `r` covers the kept step's slice of the store, or for the
+// scaled FP8 type the FP32 staging buffer; `elem` is the element index within it
+// (block offset + position).
 template <int DT>
-__device__ inline void record_b(__amdgpu_buffer_rsrc_t st, __amdgpu_buffer_rsrc_t stg, long long elem, bool on,
-                                float v) {
+__device__ inline void record_b(__amdgpu_buffer_rsrc_t r, uint32_t elem, bool on, float v) {
     const uint32_t oob = 0x80000000u;
-    if constexpr (DT == 3) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), stg, on ? (uint32_t)(elem * 4) : oob, 0, 0);
-    } else if constexpr (DT == 0) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), st, on ? (uint32_t)(elem * 4) : oob, 0, 0);
+    if constexpr (DT == 0 || DT == 3) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, on ? elem * 4 : oob, 0, 0);
     } else if constexpr (DT == 1 || DT == 2) {
         const uint16_t q = DT == 1 ? enc_fp16(v) : enc_bf16(v);
-        __builtin_amdgcn_raw_buffer_store_b16(q, st, on ? (uint32_t)(elem * 2) : oob, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(q, r, on ? elem * 2 : oob, 0, 0);
     } else {
         uint8_t q;
         if constexpr (DT == 4) q = enc_f8<4, 3, 11, 2>(v);
@@ -345,7 +343,7 @@ __device__ inline void record_b(__amdgpu_buffer_rsrc_t st, __amdgpu_buffer_rsrc_
         else if constexpr (DT == 7) q = enc_f8<4, 3, 7, 0>(v);
         else if constexpr (DT == 8) q = enc_f8<3, 4, 3, 0>(v);
         else q = enc_f8<4, 3, 7, 1>(v);
-        __builtin_amdgcn_raw_buffer_store_b8(q, st, on ? (uint32_t)elem : oob, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b8(q, r, on ? elem : oob, 0, 0);
     }
 }
 
@@ -393,6 +391,10 @@ __device__ inline float nb_minus(const float* f, long long idx, int i, int n, lo
     return periodic ? f[idx + (long long)(n - 1) * stride] : 0.0f;
 }
 
+// dt / eps of the E update; the forward step, its reversal and its adjoint all use
+// this one expression, so that they agree bit for bit.
+__device__ inline float dt_over_eps(float dt, float ep) { return __fdividef(dt, ep); }
+
 __device__ inline int slab_coord(int i, int n, int P) {   // -1 outside the slab
     if (i < P) return i;
     if (i >= n - P) return i - (n - 2 * P);
@@ -425,8 +427,8 @@ inline void launch_kernel(int kind, Kernel kernel, dim3 grid, dim3 block, hipStr
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 struct Tiling;
-void launch_fwd_step(const Grid& g, const Tiling& t, const float* E0, const float* H0, float* E1, float* H1,
-                     const float* psiH0, float* psiH1, float* psiE, const float* eps, float wave, double* partials,
+void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
+                     const float* eps, float wave, double* partials,
                      void* store, float* staging, int slice, hipStream_t s);
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s);
 void launch_loss_final(const double* partials, int steps, int per_step, double* loss, double* series,

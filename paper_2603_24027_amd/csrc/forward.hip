@@ -51,29 +51,21 @@ __device__ inline void h_terms(const float (*cur)[TY + 2][EXT], const float (*nx
     t[5] = cur[0][ey + 1][ex] - exc;   // (Hz, y, -, Ex)
 }
 
-// H^{n+1/2} = H^{n-1/2} - dt curl E with the H-side CPML; p holds the old auxiliaries
-// on entry and the new ones on return.
-__device__ inline void h_update(const Grid& g, const Col& c, int sz, float t[6], const float h0[3], float p[6],
-                                float h[3]) {
-    cpml_terms(g.coef + 6 * g.P, g.P, c, sz, t, p);
-    const float dt = g.dt;
-    h[0] = h0[0] - dt * (t[0] - t[1]);
-    h[1] = h0[1] - dt * (t[2] - t[3]);
-    h[2] = h0[2] - dt * (t[4] - t[5]);
-}
-
-// The same with the coefficients of the cell's three slabs given (branch-free CPML).
-__device__ inline void h_update_cf(float dt, const Cf& cx, const Cf& cy, const Cf& cz, float t[6], const float h0[3],
-                                   float p[6], float h[3]) {
-    cpml_apply(cx, cy, cz, t, p);
-    h[0] = h0[0] - dt * (t[0] - t[1]);
-    h[1] = h0[1] - dt * (t[2] - t[3]);
-    h[2] = h0[2] - dt * (t[4] - t[5]);
-}
-
 // Buffer resources of one forward sweep.
 struct FwdBufs {
-    rsrc_t E0, H0, E1, H1, eps, psiH0, psiH1, psiE, store, staging, src;
+    rsrc_t F0, F1, psi, eps, src;                    // fields in / out (E then H), both PML copies
+    rsrc_t rec;                                      // kept step: its store slice, or the FP32 staging
+    uint32_t hin, hout;                              // byte offsets of the H-side PML copies in / out
+};
+
+// Loop-invariant per-lane byte offsets of the forward sweep (OOB where nothing is
+// read or written): E^n of the own column (boundary rule, also for idle lanes, whose
+// values serve as neighbours) and of the ring position; the own cell (live lanes);
+// the halo cell; the source box column; PML auxiliaries of the own and halo cells.
+struct FwdLanes {
+    uint32_t eo, er, o, hc, src;
+    PsiLane po, ph;
+    bool ysl;                 // the own row lies in a y slab (uniform across a wave)
 };
 
 // Everything the forward sweep reads from memory for plane k of its column:
@@ -85,36 +77,33 @@ struct PlaneIn {
     float ph[6], pe[6], phh[6];
 };
 
+__device__ __forceinline__ uint32_t src_plane(const Grid& g, int k, uint32_t lane_src, uint32_t& s) {
+    const bool in = k >= g.src_lo[2] && k < g.src_hi[2];
+    s = uni(in ? (uint32_t)((k - g.src_lo[2]) * (g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1])) << 2 : 0u);
+    return in ? lane_src : OOB;
+}
+
 // Straight-line loads of plane k's inputs (out-of-domain and out-of-slab values read as 0).
 template <int TY>
-__device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, const FwdCtx<TY>& c, int k,
-                                              PlaneIn& d) {
-    const int N = c.N;
-    const int ok = k * c.plane;
+__device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, const FwdLanes& L,
+                                              const FwdCtx<TY>& c, int k, PlaneIn& d) {
+    const uint32_t nb = (uint32_t)c.N << 2;
     const int z1 = bound(k + 1, g.nz, g.periodic);
-    const int o1 = z1 < 0 ? -1 : z1 * c.plane;
-    const int szk = g.P > 0 ? slab_coord(k, g.nz, g.P) : -1;
-    bld3(b.E0, (c.own.xy < 0 || o1 < 0) ? -1 : c.own.xy + o1, N, d.e1);
-    bld3(b.E0, (c.ring.xy < 0 || o1 < 0) ? -1 : c.ring.xy + o1, N, d.er);
-    bld3(b.H0, c.live ? c.own.xy + ok : -1, N, d.h0);
-    bld3(b.H0, c.hc.xy >= 0 ? c.hc.xy + ok : -1, N, d.hh0);
-    const float ep = bld(b.eps, c.live ? (uint32_t)(c.own.xy + ok) << 2 : OOB);
+    const uint32_t s1 = uni(z1 < 0 ? 0u : (uint32_t)(z1 * c.plane) << 2);
+    bld3v(b.F0, z1 < 0 ? OOB : L.eo, s1, nb, d.e1);
+    bld3v(b.F0, z1 < 0 ? OOB : L.er, s1, nb, d.er);
+    const uint32_t sk = uni((uint32_t)(k * c.plane) << 2);
+    bld3v(b.F0, L.o, sk + 3 * nb, nb, d.h0);
+    bld3v(b.F0, L.hc, sk + 3 * nb, nb, d.hh0);
+    const float ep = bldv(b.eps, L.o, sk);
     d.ep = c.live ? ep : 1.0f;
-    uint32_t so = OOB;
-    if (c.live && in_box(c.x, c.y, k, g.src_lo, g.src_hi)) {
-        const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
-        so = (uint32_t)((c.x - g.src_lo[0]) + sxn * ((c.y - g.src_lo[1]) + syn * (k - g.src_lo[2]))) << 2;
-    }
-    d.sp = bld(b.src, so);
-    int po[3];
-    psi_offsets(g, c.own, k, c.live ? szk : -1, 0, po);
-    if (!c.live) po[0] = po[1] = -1;
-    bld_psi(g, b.psiH0, po, d.ph);
-    psi_offsets(g, c.own, k, c.live ? szk : -1, 1, po);
-    if (!c.live) po[0] = po[1] = -1;
-    bld_psi(g, b.psiE, po, d.pe);
-    psi_offsets(g, c.hc, k, szk, 0, po);
-    bld_psi(g, b.psiH0, po, d.phh);
+    uint32_t ss;
+    const uint32_t vs = src_plane(g, k, L.src, ss);
+    d.sp = bldv(b.src, vs, ss);
+    const PsiPlane pH = psi_plane(g, 0, k, b.hin), pE = psi_plane(g, 1, k, 0);
+    bld_psi_v(b.psi, L.po, pH, d.ph);
+    bld_psi_v(b.psi, L.po, pE, d.pe);
+    bld_psi_v(b.psi, L.ph, pH, d.phh);
 }
 
 // One plane k of the forward sweep: publish E^n(k+1) to LDS, H^{n+1/2}(k) on the own
@@ -122,19 +111,16 @@ __device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, c
 // loaded one plane ahead.  All stores are unconditional buffer stores (dropped for
 // idle lanes and cells outside a slab).
 template <int TY, int REC, int CZ>
-__device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const FwdCtx<TY>& c,
+__device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const FwdLanes& L, const FwdCtx<TY>& c,
                                           float (*sE)[3][TY + 2][EXT], float (*sH)[TY + 1][TX + 1],
                                           const CoefTile<TY, CZ>& ct, int lz, int cur, int k,
                                           const PlaneIn& in, float eo[3], float& hx_prev, float& hy_prev, double& e2,
                                           float wave) {
     const int nxt = 1 - cur;
-    const int N = c.N, P = c.P, x = c.x, y = c.y, row = c.row, lane = c.lane;
-    const int ok = k * c.plane;
-    const int szk = P > 0 ? slab_coord(k, g.nz, P) : -1;
-    int poH[3], poE[3];
-    psi_offsets(g, c.own, k, c.live ? szk : -1, 0, poH);
-    psi_offsets(g, c.own, k, c.live ? szk : -1, 1, poE);
-    if (!c.live) poH[0] = poH[1] = poE[0] = poE[1] = -1;
+    const int P = c.P, x = c.x, y = c.y, row = c.row, lane = c.lane;
+    const uint32_t nb = (uint32_t)c.N << 2;
+    const uint32_t sk = uni((uint32_t)(k * c.plane) << 2);
+    const PsiPlane pH = psi_plane(g, 0, k, b.hout), pE = psi_plane(g, 1, k, 0);
     float ph[6], phh[6], pe[6];
     #pragma unroll
     for (int t = 0; t < 6; ++t) { ph[t] = in.ph[t]; phh[t] = in.phh[t]; pe[t] = in.pe[t]; }
@@ -151,28 +137,33 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
     {
         float t[6];
         h_terms<TY>(sE[cur], sE[nxt], lane + 1, row + 1, t);
-        h_update_cf(g.dt, cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, lz), t, in.h0, ph, h);
-        if (!c.live) h[0] = h[1] = h[2] = 0.0f;
+        cpml_x(cf_x(ct, 1, lane + 1), t, ph);
+        if (L.ysl) cpml_y(cf_y(ct, 1, row + 1), t, ph);
+        if (pH.zs) cpml_z(cf_z(ct, 1, lz), t, ph);
+        const float dt = g.dt;
+        h[0] = c.live ? in.h0[0] - dt * (t[0] - t[1]) : 0.0f;
+        h[1] = c.live ? in.h0[1] - dt * (t[2] - t[3]) : 0.0f;
+        h[2] = c.live ? in.h0[2] - dt * (t[4] - t[5]) : 0.0f;
     }
-    const int idx = c.live ? c.own.xy + ok : -1;
-    bst3(b.H1, idx, N, h);
-    bst_psi(g, b.psiH1, poH, ph);
+    bst3v(b.F1, L.o, sk + 3 * nb, nb, h);
+    bst_psi_v(b.psi, L.po, pH, ph);
     if constexpr (REC >= 0) {
         // interface shell of a kept step: H^{n+1/2} on the low faces, E^n on the high faces;
-        // a cell lies on at most one face
+        // a cell lies on at most one face; the second component's block follows the first
         const bool jI = y >= P && y < g.ny - P, kI = k >= P && k < g.nz - P, iI = x >= P && x < g.nx - P;
-        int blk = 0, o = 0;
+        const uint32_t ax = (uint32_t)(g.my * g.mz), ay = (uint32_t)(g.mx * g.mz), az = (uint32_t)(g.mx * g.my);
+        uint32_t e = 0, ar = 0;
         float v0 = 0.0f, v1 = 0.0f;
         bool on = c.live;
-        if (x == P - 1 && jI && kI) { blk = 0; o = (k - P) * g.my + (y - P); v0 = h[1]; v1 = h[2]; }
-        else if (y == P - 1 && iI && kI) { blk = 2; o = (k - P) * g.mx + (x - P); v0 = h[2]; v1 = h[0]; }
-        else if (k == P - 1 && iI && jI) { blk = 4; o = (y - P) * g.mx + (x - P); v0 = h[0]; v1 = h[1]; }
-        else if (x == g.nx - P && jI && kI) { blk = 6; o = (k - P) * g.my + (y - P); v0 = eo[1]; v1 = eo[2]; }
-        else if (y == g.ny - P && iI && kI) { blk = 8; o = (k - P) * g.mx + (x - P); v0 = eo[2]; v1 = eo[0]; }
-        else if (k == g.nz - P && iI && jI) { blk = 10; o = (y - P) * g.mx + (x - P); v0 = eo[0]; v1 = eo[1]; }
+        if (x == P - 1 && jI && kI) { e = g.rec_off[0] + (k - P) * g.my + (y - P); ar = ax; v0 = h[1]; v1 = h[2]; }
+        else if (y == P - 1 && iI && kI) { e = g.rec_off[2] + (k - P) * g.mx + (x - P); ar = ay; v0 = h[2]; v1 = h[0]; }
+        else if (k == P - 1 && iI && jI) { e = g.rec_off[4] + (y - P) * g.mx + (x - P); ar = az; v0 = h[0]; v1 = h[1]; }
+        else if (x == g.nx - P && jI && kI) { e = g.rec_off[6] + (k - P) * g.my + (y - P); ar = ax; v0 = eo[1]; v1 = eo[2]; }
+        else if (y == g.ny - P && iI && kI) { e = g.rec_off[8] + (k - P) * g.mx + (x - P); ar = ay; v0 = eo[2]; v1 = eo[0]; }
+        else if (k == g.nz - P && iI && jI) { e = g.rec_off[10] + (y - P) * g.mx + (x - P); ar = az; v0 = eo[0]; v1 = eo[1]; }
         else on = false;
-        record_b<REC>(b.store, b.staging, block_offset(g, blk) + o, on, v0);
-        record_b<REC>(b.store, b.staging, block_offset(g, blk + 1) + o, on, v1);
+        record_b<REC>(b.rec, e, on, v0);
+        record_b<REC>(b.rec, e + ar, on, v1);
     }
     sH[0][row + 1][lane + 1] = h[0];
     sH[1][row + 1][lane + 1] = h[1];
@@ -182,7 +173,11 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
         if (c.hc.xy >= 0) {
             float t[6];
             h_terms<TY>(sE[cur], sE[nxt], c.hex, c.hey, t);
-            h_update_cf(g.dt, cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, lz), t, in.hh0, phh, hh);
+            cpml_apply(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, lz), t, phh);
+            const float dt = g.dt;
+            hh[0] = in.hh0[0] - dt * (t[0] - t[1]);
+            hh[1] = in.hh0[1] - dt * (t[2] - t[3]);
+            hh[2] = in.hh0[2] - dt * (t[4] - t[5]);
         }
         sH[0][c.hey][c.hex] = hh[0];
         sH[1][c.hey][c.hex] = hh[1];
@@ -197,19 +192,21 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
     t[3] = h[2] - sH[2][row + 1][lane];       // (Ey, x, -, Hz)
     t[4] = h[1] - sH[1][row + 1][lane];       // (Ez, x, +, Hy)
     t[5] = h[0] - sH[0][row][lane + 1];       // (Ez, y, -, Hx)
-    cpml_apply(cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, lz), t, pe);
-    bst_psi(g, b.psiE, poE, pe);
+    cpml_x(cf_x(ct, 0, lane + 1), t, pe);
+    if (L.ysl) cpml_y(cf_y(ct, 0, row + 1), t, pe);
+    if (pE.zs) cpml_z(cf_z(ct, 0, lz), t, pe);
+    bst_psi_v(b.psi, L.po, pE, pe);
     float u[3] = {t[0] - t[1], t[2] - t[3], t[4] - t[5]};
     const float jv = wave * in.sp;   // 0 outside the source box
     u[0] -= g.src_comp == 0 ? jv : 0.0f;
     u[1] -= g.src_comp == 1 ? jv : 0.0f;
     u[2] -= g.src_comp == 2 ? jv : 0.0f;
-    const float cc = g.dt / in.ep;
+    const float cc = dt_over_eps(g.dt, in.ep);
     float e[3];
     e[0] = eo[0] + cc * u[0];
     e[1] = eo[1] + cc * u[1];
     e[2] = eo[2] + cc * u[2];
-    bst3(b.E1, idx, N, e);
+    bst3v(b.F1, L.o, sk, nb, e);
     if (c.live && in_box(x, y, k, g.det_lo, g.det_hi))
         e2 += (double)e[0] * e[0] + (double)e[1] * e[1] + (double)e[2] * e[2];
     hx_prev = h[0];
@@ -217,22 +214,21 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
     eo[0] = in.e1[0]; eo[1] = in.e1[1]; eo[2] = in.e1[2];
 }
 
-// One full forward step n: (E^n, H^{n-1/2}) in E0/H0 -> (E^{n+1}, H^{n+1/2}) in E1/H1.
-// H-side PML auxiliaries ping-pong (psiH0 -> psiH1); E-side ones are updated in place.
+// One full forward step n: (E^n, H^{n-1/2}) in F0 -> (E^{n+1}, H^{n+1/2}) in F1 (each E
+// then H, 3 components of N cells).  The PML buffer holds two copies of the auxiliaries:
+// the H-side ones ping-pong (copy hcopy -> 1 - hcopy), the E-side ones live in copy 0
+// and are updated in place.
 // The z-march over CZ planes is unrolled and software-pipelined: the loads of plane
 // k+1 are issued before the stores of plane k into the other of two register sets,
 // so no wait for them also waits for those stores (loads and stores retire in order).
-template <int TY, int REC, int CZ>
 #ifndef FDTD_FWD_WAVES
 #define FDTD_FWD_WAVES 1
 #endif
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FWD_WAVES))) void k_fwd_step(Grid g, Tiling tl, const float* __restrict__ E0,
-                                                      const float* __restrict__ H0, float* __restrict__ E1,
-                                                      float* __restrict__ H1, const float* __restrict__ psiH0,
-                                                      float* __restrict__ psiH1, float* __restrict__ psiE,
-                                                      const float* __restrict__ eps, float wave,
-                                                      double* __restrict__ partials, void* __restrict__ store,
-                                                      float* __restrict__ staging, int slice) {
+template <int TY, int REC, int CZ>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FWD_WAVES))) void k_fwd_step(
+    Grid g, Tiling tl, const float* __restrict__ F0, float* __restrict__ F1, float* __restrict__ psi, int hcopy,
+    const float* __restrict__ eps, float wave, double* __restrict__ partials, void* __restrict__ store,
+    float* __restrict__ staging, int slice) {
     __shared__ float sE[2][3][TY + 2][EXT];
     __shared__ float sH[3][TY + 1][TX + 1];
     __shared__ CoefTile<TY, CZ> ct;
@@ -254,22 +250,21 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     c.P = g.P;
     c.plane = g.nx * g.ny;
     const int N = c.N, P = c.P, plane = c.plane, lane = c.lane, row = c.row;
+    const uint32_t nb = (uint32_t)N << 2;
     FwdBufs b;
-    const uint32_t fbytes = (uint32_t)(3 * N) * 4u, psib = (uint32_t)g.psi_total * 4u;
-    b.E0 = make_rsrc(E0, fbytes);
-    b.H0 = make_rsrc(H0, fbytes);
-    b.E1 = make_rsrc(E1, fbytes);
-    b.H1 = make_rsrc(H1, fbytes);
+    const uint32_t fbytes = (uint32_t)(6 * N) * 4u, psib = (uint32_t)g.psi_total * 4u;
+    b.F0 = make_rsrc(F0, fbytes);
+    b.F1 = make_rsrc(F1, fbytes);
+    b.psi = make_rsrc(psi, 2 * psib);
+    b.hin = hcopy ? psib : 0u;
+    b.hout = hcopy ? 0u : psib;
     b.eps = make_rsrc(eps, (uint32_t)N * 4u);
-    b.psiH0 = make_rsrc(psiH0, psib);
-    b.psiH1 = make_rsrc(psiH1, psib);
-    b.psiE = make_rsrc(psiE, psib);
-    // the kept step's slice of the store (a store can exceed 4 GiB; one slice cannot)
-    b.store = make_rsrc(store ? (char*)store + (long long)slice * g.slice_stride : nullptr,
-                        store ? (uint32_t)g.slice_stride : 0u);
-    b.staging = make_rsrc(staging, g.dtype == 3 ? (uint32_t)g.vps * 4u : 0u);
-    b.src = make_rsrc(g.src_profile, (uint32_t)((g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1]) *
-                                                (g.src_hi[2] - g.src_lo[2])) * 4u);
+    // a kept step records into its slice of the store (a store can exceed 4 GiB; one
+    // slice cannot), the scaled FP8 type into the FP32 staging buffer
+    if constexpr (REC == 3) b.rec = make_rsrc(staging, (uint32_t)g.vps * 4u);
+    else if constexpr (REC >= 0) b.rec = make_rsrc((char*)store + (long long)slice * g.slice_stride, (uint32_t)g.slice_stride);
+    const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
+    b.src = make_rsrc(g.src_profile, (uint32_t)(sxn * syn * (g.src_hi[2] - g.src_lo[2])) * 4u);
 
     // columns this thread touches: its own, one position of the LDS ring, one halo H cell
     c.own = make_col(g, c.x, c.y);
@@ -281,14 +276,25 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     else if (row == 3 && lane < TY + 2) { c.rlx = EXT - 1; c.rly = lane; c.ring = make_col(g, c.i0 + TX, c.j0 - 1 + lane); }
     c.hex = c.hey = -1;
     c.hc.xy = -1;
+    c.hc.x = c.hc.y = 0;
     c.hc.sx = c.hc.sy = -1;
     if (c.tid < TX + TY) {
         if (c.tid < TX) { c.hex = c.tid + 1; c.hey = 0; } else { c.hex = 0; c.hey = c.tid - TX + 1; }
         const int xr = c.i0 - 1 + c.hex, yr = c.j0 - 1 + c.hey;
         if (xr < g.nx && yr < g.ny) c.hc = make_col(g, xr, yr);   // positions past the far edge are never read
     }
-
+    FwdLanes Ln;
+    Ln.eo = lane_off(c.own.xy >= 0, c.own.xy);
+    Ln.er = lane_off(c.ring.xy >= 0, c.ring.xy);
+    Ln.o = lane_off(c.live, c.own.xy);
+    Ln.hc = lane_off(c.hc.xy >= 0, c.hc.xy);
+    Ln.src = lane_off(c.live && c.x >= g.src_lo[0] && c.x < g.src_hi[0] && c.y >= g.src_lo[1] && c.y < g.src_hi[1],
+                      (c.x - g.src_lo[0]) + sxn * (c.y - g.src_lo[1]));
+    Ln.po = psi_lane(g, c.own, c.live);
+    Ln.ph = psi_lane(g, c.hc, c.hc.xy >= 0);
+    Ln.ysl = c.own.sy >= 0;
     fill_coef_tile<TY, CZ>(g, ct, c.i0, c.j0, k0, c.tid, TX * TY);   // published by the prologue's barrier
+
     // prologue: E^n planes k0-1 and k0 into LDS, H^{n+1/2} of this column at k0-1, and
     // the inputs of plane k0
     PlaneIn pin[2];
@@ -296,20 +302,20 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     float hx_prev, hy_prev;            // H^{n+1/2} of the own cell on the previous plane
     {
         const int zm = bound(k0 - 1, g.nz, g.periodic);
-        const int om = zm < 0 ? -1 : zm * plane;
-        const int szm = (zm >= 0 && P > 0) ? slab_coord(zm, g.nz, P) : -1;
+        const uint32_t sm = uni(zm < 0 ? 0u : (uint32_t)(zm * plane) << 2), s0 = uni((uint32_t)(k0 * plane) << 2);
         float a[3], ra[3], rb[3], h0[3], p[6];
-        bld3(b.E0, (c.own.xy < 0 || om < 0) ? -1 : c.own.xy + om, N, a);
-        bld3(b.E0, c.own.xy < 0 ? -1 : c.own.xy + k0 * plane, N, eo);
-        bld3(b.E0, (c.ring.xy < 0 || om < 0) ? -1 : c.ring.xy + om, N, ra);
-        bld3(b.E0, c.ring.xy < 0 ? -1 : c.ring.xy + k0 * plane, N, rb);
+        bld3v(b.F0, zm < 0 ? OOB : Ln.eo, sm, nb, a);
+        bld3v(b.F0, Ln.eo, s0, nb, eo);
+        bld3v(b.F0, zm < 0 ? OOB : Ln.er, sm, nb, ra);
+        bld3v(b.F0, Ln.er, s0, nb, rb);
         const bool pro = c.live && zm >= 0;
-        bld3(b.H0, pro ? c.own.xy + om : -1, N, h0);
-        int po[3];
-        psi_offsets(g, c.own, zm, pro ? szm : -1, 0, po);
-        if (!pro) po[0] = po[1] = -1;
-        bld_psi(g, b.psiH0, po, p);
-        load_plane_in<TY>(g, b, c, k0, pin[0]);
+        bld3v(b.F0, zm < 0 ? OOB : Ln.o, sm + 3 * nb, nb, h0);
+        PsiPlane pm = psi_plane(g, 0, zm < 0 ? 0 : zm, b.hin);
+        pm.zs = pm.zs && zm >= 0;
+        PsiLane lm = Ln.po;
+        if (zm < 0) lm.x = lm.y = lm.z = OOB;
+        bld_psi_v(b.psi, lm, pm, p);
+        load_plane_in<TY>(g, b, Ln, c, k0, pin[0]);
         #pragma unroll
         for (int q = 0; q < 3; ++q) {
             sE[0][q][row + 1][lane + 1] = a[q];
@@ -320,11 +326,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
             for (int q = 0; q < 3; ++q) { sE[0][q][c.rly][c.rlx] = ra[q]; sE[1][q][c.rly][c.rlx] = rb[q]; }
         }
         __syncthreads();
-        float t[6], h[3];
+        float t[6];
         h_terms<TY>(sE[0], sE[1], lane + 1, row + 1, t);
-        h_update_cf(g.dt, cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), t, h0, p, h);
-        hx_prev = pro ? h[0] : 0.0f;
-        hy_prev = pro ? h[1] : 0.0f;
+        cpml_apply(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), t, p);
+        hx_prev = pro ? h0[0] - g.dt * (t[0] - t[1]) : 0.0f;
+        hy_prev = pro ? h0[1] - g.dt * (t[2] - t[3]) : 0.0f;
     }
     __syncthreads();   // the first plane overwrites sE[0], which the prologue has just read
     double e2 = 0.0;
@@ -333,10 +339,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     for (int kk = 0; kk < CZ; ++kk) {
         const int k = k0 + kk;
         if (kk + 1 < CZ)   // inputs of the next plane (an unused valid plane past the end of the grid)
-            load_plane_in<TY>(g, b, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+            load_plane_in<TY>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
         if (k < k1)
-            fwd_plane<TY, REC, CZ>(g, b, c, sE, sH, ct, kk + 1, (kk + 1) & 1, k, pin[kk & 1], eo, hx_prev, hy_prev, e2,
-                                   wave);
+            fwd_plane<TY, REC, CZ>(g, b, Ln, c, sE, sH, ct, kk + 1, (kk + 1) & 1, k, pin[kk & 1], eo, hx_prev,
+                                   hy_prev, e2, wave);
     }
     // detector partial of this tile (tiles intersecting the detector only; uniform per block)
     const int dx = tix - tl.dtx0, dy = tiy - tl.dty0, dz = tiz - tl.dtz0;
@@ -398,32 +404,32 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
 }
 
 template <int TY, int CZ>
-static void launch_fwd_step_t(const Grid& g, const Tiling& t, const float* E0, const float* H0, float* E1, float* H1,
-                              const float* psiH0, float* psiH1, float* psiE, const float* eps, float wave,
-                              double* partials, void* store, float* staging, int slice, hipStream_t s) {
+static void launch_fwd_step_t(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
+                              const float* eps, float wave, double* partials, void* store, float* staging, int slice,
+                              hipStream_t s) {
     const dim3 grid(t.count), block(TX, TY);
     if (slice < 0 || g.P == 0) {
-        launch_kernel(K_FWD_STEP, k_fwd_step<TY, -1, CZ>, grid, block, s, g, t, E0, H0, E1, H1, psiH0, psiH1, psiE,
-                      eps, wave, partials, store, staging, slice);
+        launch_kernel(K_FWD_STEP, k_fwd_step<TY, -1, CZ>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
+                      partials, store, staging, slice);
         return;
     }
     with_dtype(g.dtype, [&]<int DT>() {
-        launch_kernel(K_FWD_STEP, k_fwd_step<TY, DT, CZ>, grid, block, s, g, t, E0, H0, E1, H1, psiH0, psiH1, psiE,
-                      eps, wave, partials, store, staging, slice);
+        launch_kernel(K_FWD_STEP, k_fwd_step<TY, DT, CZ>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
+                      partials, store, staging, slice);
     });
 }
 
-void launch_fwd_step(const Grid& g, const Tiling& t, const float* E0, const float* H0, float* E1, float* H1,
-                     const float* psiH0, float* psiH1, float* psiE, const float* eps, float wave, double* partials,
-                     void* store, float* staging, int slice, hipStream_t s) {
+void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
+                     const float* eps, float wave, double* partials, void* store, float* staging, int slice,
+                     hipStream_t s) {
     if (t.ty == 4 && t.cz == 4)
-        launch_fwd_step_t<4, 4>(g, t, E0, H0, E1, H1, psiH0, psiH1, psiE, eps, wave, partials, store, staging, slice, s);
+        launch_fwd_step_t<4, 4>(g, t, F0, F1, psi, hcopy, eps, wave, partials, store, staging, slice, s);
     else if (t.ty == 4)
-        launch_fwd_step_t<4, 8>(g, t, E0, H0, E1, H1, psiH0, psiH1, psiE, eps, wave, partials, store, staging, slice, s);
+        launch_fwd_step_t<4, 8>(g, t, F0, F1, psi, hcopy, eps, wave, partials, store, staging, slice, s);
     else if (t.cz == 4)
-        launch_fwd_step_t<8, 4>(g, t, E0, H0, E1, H1, psiH0, psiH1, psiE, eps, wave, partials, store, staging, slice, s);
+        launch_fwd_step_t<8, 4>(g, t, F0, F1, psi, hcopy, eps, wave, partials, store, staging, slice, s);
     else
-        launch_fwd_step_t<8, 8>(g, t, E0, H0, E1, H1, psiH0, psiH1, psiE, eps, wave, partials, store, staging, slice, s);
+        launch_fwd_step_t<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, partials, store, staging, slice, s);
 }
 
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s) {

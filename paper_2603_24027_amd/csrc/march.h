@@ -277,4 +277,90 @@ __device__ inline void cpml_apply(const Cf& cx, const Cf& cy, const Cf& cz, floa
     p[2] = cz.b * p[2] + cz.a * t[2]; t[2] = cz.k * t[2] + p[2];
 }
 
+// Loads and stores addressed as a per-lane byte offset v (loop-invariant: the
+// lane's column, or OOB) plus a wave-uniform byte offset s (plane, component),
+// so that the z-march spends no vector instructions on addresses.  An OOB lane
+// offset stays out of range whatever s is added (every buffer is below 2 GiB).
+__device__ inline float bldv(rsrc_t r, uint32_t v, uint32_t s) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+}
+__device__ inline void bstv(rsrc_t r, uint32_t v, uint32_t s, float x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, 0);
+}
+// three components of a field: component c at s + c * nb (nb = 4 N)
+__device__ inline void bld3v(rsrc_t r, uint32_t v, uint32_t s, uint32_t nb, float o[3]) {
+    o[0] = bldv(r, v, s);
+    o[1] = bldv(r, v, s + nb);
+    o[2] = bldv(r, v, s + 2 * nb);
+}
+__device__ inline void bst3v(rsrc_t r, uint32_t v, uint32_t s, uint32_t nb, const float o[3]) {
+    bstv(r, v, s, o[0]);
+    bstv(r, v, s + nb, o[1]);
+    bstv(r, v, s + 2 * nb, o[2]);
+}
+__device__ inline uint32_t lane_off(bool on, int idx) { return on ? (uint32_t)idx << 2 : OOB; }
+// a value the caller knows to be wave-uniform, kept in a scalar register (the buffer
+// instructions take their uniform offset from one)
+__device__ inline uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// Per-lane part of the byte offsets of a column's PML auxiliaries: x slab
+// sx + 2P y, y slab x + nx sy, z slab x + nx y (OOB outside the slab or when off).
+struct PsiLane {
+    uint32_t x, y, z;
+};
+__device__ inline PsiLane psi_lane(const Grid& g, const Col& c, bool on) {
+    PsiLane l;
+    l.x = lane_off(on && c.sx >= 0, c.sx + 2 * g.P * c.y);
+    l.y = lane_off(on && c.sy >= 0, c.x + g.nx * c.sy);
+    l.z = lane_off(on && c.xy >= 0 && g.P > 0, c.xy);
+    return l;
+}
+// Plane-uniform part for one side (0 H, 1 E) on plane z of the copy at byte offset
+// `base`, and the distance to the second auxiliary of each slab.
+struct PsiPlane {
+    uint32_t x, y, z, dx, dy, dz;
+    bool zs;                  // plane z lies in a z slab
+};
+__device__ inline PsiPlane psi_plane(const Grid& g, int side, int z, uint32_t base) {
+    PsiPlane p;
+    const int P = g.P;
+    const int sz = P > 0 ? slab_coord(z, g.nz, P) : -1;
+    p.zs = sz >= 0;
+    p.x = uni(base + ((uint32_t)(g.psi_off[0] + side * 2 * g.slab[0] + 2LL * P * g.ny * z) << 2));
+    p.y = uni(base + ((uint32_t)(g.psi_off[1] + side * 2 * g.slab[1] + 2LL * P * g.nx * z) << 2));
+    p.z = uni(base + ((uint32_t)(g.psi_off[2] + side * 2 * g.slab[2] + (long long)g.nx * g.ny * (p.zs ? sz : 0)) << 2));
+    p.dx = (uint32_t)g.slab[0] << 2;
+    p.dy = (uint32_t)g.slab[1] << 2;
+    p.dz = (uint32_t)g.slab[2] << 2;
+    return p;
+}
+// the six auxiliaries (x: 3, 4; y: 0, 5; z: 1, 2); 0 outside the slabs
+__device__ inline void bld_psi_v(rsrc_t r, const PsiLane& l, const PsiPlane& p, float v[6]) {
+    const uint32_t vz = p.zs ? l.z : OOB;
+    v[3] = bldv(r, l.x, p.x); v[4] = bldv(r, l.x, p.x + p.dx);
+    v[0] = bldv(r, l.y, p.y); v[5] = bldv(r, l.y, p.y + p.dy);
+    v[1] = bldv(r, vz, p.z); v[2] = bldv(r, vz, p.z + p.dz);
+}
+__device__ inline void bst_psi_v(rsrc_t r, const PsiLane& l, const PsiPlane& p, const float v[6]) {
+    const uint32_t vz = p.zs ? l.z : OOB;
+    bstv(r, l.x, p.x, v[3]); bstv(r, l.x, p.x + p.dx, v[4]);
+    bstv(r, l.y, p.y, v[0]); bstv(r, l.y, p.y + p.dy, v[5]);
+    bstv(r, vz, p.z, v[1]); bstv(r, vz, p.z + p.dz, v[2]);
+}
+
+// CPML of one axis on its two terms (see cpml_apply); the y and z parts run under
+// wave-uniform branches, the x part (which varies across a wave) always.
+__device__ inline void cpml_x(const Cf& c, float t[6], float p[6]) {
+    p[3] = c.b * p[3] + c.a * t[3]; t[3] = c.k * t[3] + p[3];
+    p[4] = c.b * p[4] + c.a * t[4]; t[4] = c.k * t[4] + p[4];
+}
+__device__ inline void cpml_y(const Cf& c, float t[6], float p[6]) {
+    p[0] = c.b * p[0] + c.a * t[0]; t[0] = c.k * t[0] + p[0];
+    p[5] = c.b * p[5] + c.a * t[5]; t[5] = c.k * t[5] + p[5];
+}
+__device__ inline void cpml_z(const Cf& c, float t[6], float p[6]) {
+    p[1] = c.b * p[1] + c.a * t[1]; t[1] = c.k * t[1] + p[1];
+    p[2] = c.b * p[2] + c.a * t[2]; t[2] = c.k * t[2] + p[2];
+}
+
 }  // namespace fdtd

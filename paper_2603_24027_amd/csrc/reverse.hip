@@ -112,7 +112,7 @@ __device__ __forceinline__ void load_adj_in(const Grid& g, const AdjBufs& b, con
 // (vx, -vx, vy, -vy, vz, -vz), CPML transpose; the new auxiliaries go to pout.
 __device__ __forceinline__ void ge_terms(float dt, const float eb[3], float ep, const float pe[6], const Cf& cx,
                                          const Cf& cy, const Cf& cz, float o[6], float pout[6]) {
-    const float cc = dt / ep;
+    const float cc = dt_over_eps(dt, ep);
     const float vx = cc * eb[0], vy = cc * eb[1], vz = cc * eb[2];
     o[0] = vx; o[1] = -vx; o[2] = vy; o[3] = -vy; o[4] = vz; o[5] = -vz;
     gbar_apply(cx, cy, cz, o, pe, pout);
@@ -385,7 +385,7 @@ __device__ __forceinline__ void e_rev(const Grid& g, const float (*hc)[TY + 2][E
     u[0] -= g.src_comp == 0 ? jv : 0.0f;
     u[1] -= g.src_comp == 1 ? jv : 0.0f;
     u[2] -= g.src_comp == 2 ? jv : 0.0f;
-    const float cc = g.dt / ep;
+    const float cc = dt_over_eps(g.dt, ep);
     e[0] = interior ? e1[0] - cc * u[0] : 0.0f;
     e[1] = interior ? e1[1] - cc * u[1] : 0.0f;
     e[2] = interior ? e1[2] - cc * u[2] : 0.0f;
