@@ -50,6 +50,7 @@ struct Plan {
     Tiling fwd;            // forward and adjoint sweeps: the whole grid
     Tiling rev;            // primal reversal: the interior plus its shell
     int box_o[3], box_n[3];
+    int rev_x0;                    // x origin of the primal-reversal tiles (128-byte aligned)
     fdtd_store_info_t info;
     uint64_t ws_coef = 0, ws_profile = 0, ws_partials = 0, ws_staging = 0, ws_fields = 0;
     uint64_t psi_floats = 0;
@@ -180,7 +181,8 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     r = t;
     r.ty = env_int("FDTD_REV_TILE_Y", t.ty) == 8 ? 8 : 4;
     r.cz = env_int("FDTD_REV_TILE_Z", t.cz) == 8 ? 8 : 4;
-    r.ntx = (pl->box_n[0] + TX - 1) / TX;
+    pl->rev_x0 = pl->box_o[0] & ~31;
+    r.ntx = (pl->box_o[0] + pl->box_n[0] - pl->rev_x0 + TX - 1) / TX;
     r.nty = (pl->box_n[1] + r.ty - 1) / r.ty;
     r.ntz = (pl->box_n[2] + r.cz - 1) / r.cz;
     r.count = r.ntx * r.nty * r.ntz;
@@ -451,16 +453,19 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
         launch_fill(Fa[0], 6 * N, 0.0f, q);
         launch_fill(adj_psi, 2 * (long long)pl.psi_floats, 0.0f, q);
         launch_fill_f64(grad_eps, (long long)pl.info.design_cells, 0.0, q);
-        launch_inject_h(g, Fp[0] + 3 * N, store, interp_for(T - 1, T, k), q);
+        const Interp none{-1, 0, 0.0f, 0.0f};
+        launch_inject_shell(g, Fp[0], store, none, interp_for(T - 1, T, k), 0, 1, q);
         for (int n = T - 1; n >= 0; --n) {
             const int st = T - 1 - n;
             float* po = Fp[st & 1];
             float* pn = Fp[(st + 1) & 1];
             float* ao = Fa[st & 1];
             float* an = Fa[(st + 1) & 1];
-            const Interp qh = n >= 1 ? interp_for(n - 1, T, k) : Interp{-1, 0, 0.0f, 0.0f};
-            launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, po, po + 3 * N, pn, pn + 3 * N, eps, ao, store,
-                            interp_for(n, T, k), qh, n >= 1, wave[n], grad_eps, q);
+            // the interface shell of the output state (E^n high faces, H^{n-1/2} low faces), then
+            // the interior reversal, which reads the E part of that shell
+            launch_inject_shell(g, pn, store, interp_for(n, T, k), n >= 1 ? interp_for(n - 1, T, k) : none, 1, n >= 1,
+                                q);
+            launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], grad_eps, q);
             launch_adj_step(g, pl.fwd, ao, ao + 3 * N, an, an + 3 * N, eps, psi_buf[st & 1],
                             psi_buf[(st + 1) & 1], q);
         }

@@ -433,10 +433,11 @@ void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1,
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s);
 void launch_loss_final(const double* partials, int steps, int per_step, double* loss, double* series,
                        hipStream_t s);
-void launch_inject_h(const Grid& g, float* H, const void* store, Interp q, hipStream_t s);
-void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], const float* E0,
-                     const float* H0, float* E1, float* H1, const float* eps, float* Eb0, const void* store,
-                     Interp qE, Interp qH, int inject_h, float wave, double* grad, hipStream_t s);
+void launch_inject_shell(const Grid& g, float* F, const void* store, Interp qE, Interp qH, int do_e, int do_h,
+                         hipStream_t s);
+void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
+                     const float* F0, float* F1, const float* eps, float* Eb0, float wave, double* grad,
+                     hipStream_t s);
 void launch_adj_step(const Grid& g, const Tiling& t, const float* Eb0, const float* Hb0, float* Eb1, float* Hb1,
                      const float* eps, const float* psi_in, float* psi_out, hipStream_t s);
 void launch_scale_grad(double* grad, long long n, const double* scale, hipStream_t s);

@@ -317,10 +317,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
 struct Box {            // the region prim_rev sweeps: I plus a one-cell shell
     int o[3];           // origin
     int n[3];           // extent
+    int tx0;            // x origin of the tiles: o[0] rounded down to a 128-byte line
 };
 
 struct RevBufs {
-    rsrc_t E0, H0, E1, H1, eps, src;
+    rsrc_t F0, F1, eps, src;   // primal fields in / out (E then H)
 };
 
 // What the primal reversal reads for plane k, loaded one plane ahead: H^{n+1/2}
@@ -328,6 +329,16 @@ struct RevBufs {
 // profile at plane k+1 (own cell and the extra +x / +y position).
 struct RevIn {
     float h[3], rh[3], e[3], xe[3], ep, xep, sp, xsp;
+    float sh[3], xsh[3];      // E^n of the high-face interface shell (0 elsewhere)
+};
+
+// Loop-invariant per-lane byte offsets: H of the own column and ring position
+// (boundary rule), E^{n+1}/eps of the own and extra positions where they are
+// interior in x and y, the source box column of both, the own cell's stores, and
+// the high-face shell cells of both positions (shk: on the x or y face, for
+// interior planes; shz: interior in x and y, for the z face plane).
+struct RevLanes {
+    uint32_t h, r, e, xe, src, xsrc, st, shk, shz, xshk, xshz;
 };
 
 template <int TY>
@@ -338,41 +349,53 @@ struct RevCtx {
     int rlx, rly, pex, pey;
 };
 
-__device__ __forceinline__ uint32_t src_off(const Grid& g, const Col& c, int z) {
-    if (c.xy < 0 || z < 0) return OOB;
-    if (!in_box(c.x, c.y, z, g.src_lo, g.src_hi)) return OOB;
-    const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
-    return (uint32_t)((c.x - g.src_lo[0]) + sxn * ((c.y - g.src_lo[1]) + syn * (z - g.src_lo[2]))) << 2;
+__device__ inline bool xy_interior(const Grid& g, const Col& c) {
+    return c.xy >= 0 && c.x >= g.P && c.x < g.nx - g.P && c.y >= g.P && c.y < g.ny - g.P;
 }
-
-// E^{n+1}, eps and source profile of column c on plane z (z < 0 or outside: 0, eps 1)
-__device__ __forceinline__ void load_e_in(const Grid& g, const RevBufs& b, const Col& c, int z, int plane,
-                                          float e[3], float& ep, float& sp) {
-    const int idx = (c.xy < 0 || z < 0) ? -1 : c.xy + z * plane;
-    bld3(b.E0, idx, (int)g.N, e);
-    const float v = bld(b.eps, idx < 0 ? OOB : (uint32_t)idx << 2);
-    ep = idx < 0 ? 1.0f : v;
-    sp = bld(b.src, src_off(g, c, z));
+__device__ inline uint32_t src_lane(const Grid& g, const Col& c) {
+    const bool in = c.xy >= 0 && c.x >= g.src_lo[0] && c.x < g.src_hi[0] && c.y >= g.src_lo[1] && c.y < g.src_hi[1];
+    return lane_off(in, (c.x - g.src_lo[0]) + (g.src_hi[0] - g.src_lo[0]) * (c.y - g.src_lo[1]));
 }
+// uniform byte offset of plane z in the source profile, and whether z crosses the source box
+__device__ inline bool src_z(const Grid& g, int z, uint32_t& s) {
+    const bool in = z >= g.src_lo[2] && z < g.src_hi[2];
+    s = uni(in ? (uint32_t)((z - g.src_lo[2]) * (g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1])) << 2 : 0u);
+    return in;
+}
+__device__ inline bool z_interior(const Grid& g, int z) { return z >= g.P && z < g.nz - g.P; }
 
 template <int TY>
-__device__ __forceinline__ void load_rev_in(const Grid& g, const RevBufs& b, const RevCtx<TY>& c, int k, RevIn& d) {
+__device__ __forceinline__ void load_rev_in(const Grid& g, const RevBufs& b, const RevLanes& L, const RevCtx<TY>& c,
+                                            int k, RevIn& d) {
+    const uint32_t nb = (uint32_t)c.N << 2;
     const int z1 = bound(k + 1, g.nz, g.periodic);
-    bld3(b.H0, (c.own.xy < 0 || z1 < 0) ? -1 : c.own.xy + z1 * c.plane, c.N, d.h);
-    bld3(b.H0, (c.ring.xy < 0 || z1 < 0) ? -1 : c.ring.xy + z1 * c.plane, c.N, d.rh);
-    load_e_in(g, b, c.own, z1, c.plane, d.e, d.ep, d.sp);
-    load_e_in(g, b, c.xcol, z1, c.plane, d.xe, d.xep, d.xsp);
+    const uint32_t s1 = uni(z1 < 0 ? 0u : (uint32_t)(z1 * c.plane) << 2);
+    bld3v(b.F0, z1 < 0 ? OOB : L.h, s1 + 3 * nb, nb, d.h);
+    bld3v(b.F0, z1 < 0 ? OOB : L.r, s1 + 3 * nb, nb, d.rh);
+    const bool zi = z1 >= 0 && z_interior(g, z1);
+    bld3v(b.F0, zi ? L.e : OOB, s1, nb, d.e);
+    bld3v(b.F0, zi ? L.xe : OOB, s1, nb, d.xe);
+    const float ep = bldv(b.eps, zi ? L.e : OOB, s1), xep = bldv(b.eps, zi ? L.xe : OOB, s1);
+    d.ep = ep == 0.0f ? 1.0f : ep;      // positions that are not interior read 0
+    d.xep = xep == 0.0f ? 1.0f : xep;
+    uint32_t ss;
+    const bool sz = z1 >= 0 && src_z(g, z1, ss);
+    d.sp = bldv(b.src, sz ? L.src : OOB, ss);
+    d.xsp = bldv(b.src, sz ? L.xsrc : OOB, ss);
+    // the shell values were written into the output buffer before this sweep
+    const bool zh = z1 >= 0 && z1 == g.nz - g.P;
+    bld3v(b.F1, zi ? L.shk : (zh ? L.shz : OOB), s1, nb, d.sh);
+    bld3v(b.F1, zi ? L.xshk : (zh ? L.xshz : OOB), s1, nb, d.xsh);
 }
 
 // E^n at one position of plane z (column col, wrapped; extended-plane coordinates
 // (ex, ey) of the LDS H planes at z (hc) and z-1 (hp)).  Interior cells are
 // reversed, E^n = E^{n+1} - (dt/eps)(curl H - J); high-face shell cells take the
-// recorded values; anything else is 0.  u returns curl H - J (interior cells).
-template <int TY, int DT>
+// recorded values sh (0 for anything else).  u returns curl H - J (interior cells).
+template <int TY>
 __device__ __forceinline__ void e_rev(const Grid& g, const float (*hc)[TY + 2][EXT], const float (*hp)[TY + 2][EXT],
                                       int ex, int ey, const Col& col, int z, const float e1[3], float ep, float sp,
-                                      float wave, const void* __restrict__ store, const Interp& qE, float e[3],
-                                      float u[3], bool& interior) {
+                                      const float sh[3], float wave, float e[3], float u[3], bool& interior) {
     const int P = g.P, x = col.x, y = col.y;
     const bool inside = col.xy >= 0 && z >= 0;
     const bool iI = x >= P && x < g.nx - P, jI = y >= P && y < g.ny - P, kI = z >= P && z < g.nz - P;
@@ -386,24 +409,9 @@ __device__ __forceinline__ void e_rev(const Grid& g, const float (*hc)[TY + 2][E
     u[1] -= g.src_comp == 1 ? jv : 0.0f;
     u[2] -= g.src_comp == 2 ? jv : 0.0f;
     const float cc = dt_over_eps(g.dt, ep);
-    e[0] = interior ? e1[0] - cc * u[0] : 0.0f;
-    e[1] = interior ? e1[1] - cc * u[1] : 0.0f;
-    e[2] = interior ? e1[2] - cc * u[2] : 0.0f;
-    if (P > 0 && inside && !interior) {     // high-face interface shell (rare)
-        if (x == g.nx - P && jI && kI) {
-            const int o = (z - P) * g.my + (y - P);
-            e[1] = shell_value_t<DT>(g, store, qE, 6, o);
-            e[2] = shell_value_t<DT>(g, store, qE, 7, o);
-        } else if (y == g.ny - P && iI && kI) {
-            const int o = (z - P) * g.mx + (x - P);
-            e[2] = shell_value_t<DT>(g, store, qE, 8, o);
-            e[0] = shell_value_t<DT>(g, store, qE, 9, o);
-        } else if (z == g.nz - P && iI && jI) {
-            const int o = (y - P) * g.mx + (x - P);
-            e[0] = shell_value_t<DT>(g, store, qE, 10, o);
-            e[1] = shell_value_t<DT>(g, store, qE, 11, o);
-        }
-    }
+    e[0] = interior ? e1[0] - cc * u[0] : sh[0];
+    e[1] = interior ? e1[1] - cc * u[1] : sh[1];
+    e[2] = interior ? e1[2] - cc * u[2] : sh[2];
 }
 
 // The owner of an interior cell on the design or detector box: this step's loss
@@ -435,48 +443,50 @@ __device__ __forceinline__ void grad_and_seed(const Grid& g, float* __restrict__
 
 // E^n of plane z on the own cell (written by its owner, with gradient and seed) and the
 // extra position, into the LDS plane sE.
-template <int TY, int DT>
-__device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const RevCtx<TY>& c,
+template <int TY>
+__device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const RevLanes& L, const RevCtx<TY>& c,
                                         float (*sE)[TY + 1][TX + 1], const float (*hc)[TY + 2][EXT],
                                         const float (*hp)[TY + 2][EXT], int z, bool owned, const float e1[3], float ep,
-                                        float sp, const float xe1[3], float xep, float xsp, float wave,
-                                        const void* __restrict__ store, const Interp& qE, float* __restrict__ Eb0,
+                                        float sp, const float sh[3], const float xe1[3], float xep, float xsp,
+                                        const float xsh[3], float wave, float* __restrict__ Eb0,
                                         double* __restrict__ grad) {
     const int lane = c.lane, row = c.row;
     float e[3], u[3];
     bool interior;
-    e_rev<TY, DT>(g, hc, hp, lane + 1, row + 1, c.own, z, e1, ep, sp, wave, store, qE, e, u, interior);
+    e_rev<TY>(g, hc, hp, lane + 1, row + 1, c.own, z, e1, ep, sp, sh, wave, e, u, interior);
     sE[0][row][lane] = e[0];
     sE[1][row][lane] = e[1];
     sE[2][row][lane] = e[2];
-    const bool w = owned && c.live && interior;
-    const int idx = w ? c.own.xy + z * c.plane : -1;
-    bst3(b.E1, idx, c.N, e);
-    if (w) grad_and_seed(g, Eb0, grad, c.own.x, c.own.y, z, idx, e1, ep, u);
+    // own interior cell: store (its lane offset is OOB unless live and interior in x and y)
+    const bool zst = owned && z >= 0 && z_interior(g, z);
+    const uint32_t nb = (uint32_t)c.N << 2;
+    bst3v(b.F1, zst ? L.st : OOB, uni(zst ? (uint32_t)(z * c.plane) << 2 : 0u), nb, e);
+    if (owned && c.live && interior) grad_and_seed(g, Eb0, grad, c.own.x, c.own.y, z, c.own.xy + z * c.plane, e1, ep, u);
     if (c.pex >= 0) {
-        e_rev<TY, DT>(g, hc, hp, c.pex + 1, c.pey + 1, c.xcol, z, xe1, xep, xsp, wave, store, qE, e, u, interior);
+        e_rev<TY>(g, hc, hp, c.pex + 1, c.pey + 1, c.xcol, z, xe1, xep, xsp, xsh, wave, e, u, interior);
         sE[0][c.pey][c.pex] = e[0];
         sE[1][c.pey][c.pex] = e[1];
         sE[2][c.pey][c.pex] = e[2];
     }
 }
 
-// One reverse primal step over the box: (E^{n+1}, H^{n+1/2}) in E0/H0 -> (E^n, H^{n-1/2})
-// in E1/H1 on the interior, the shell values from the store, gradient and loss seed.
+// One reverse primal step over the box: (E^{n+1}, H^{n+1/2}) in F0 -> (E^n, H^{n-1/2})
+// in F1 on the interior, with the gradient and the loss seed.  The interface shell of
+// F1 (E^n on the high faces, H^{n-1/2} on the low faces) is written beforehand from the
+// store (k_inject_shell); the sweep reads the E part of it.
 #ifndef FDTD_REV_WAVES
 #define FDTD_REV_WAVES 1
 #endif
-template <int TY, int DT, int CZ>
+template <int TY, int CZ>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_REV_WAVES))) void k_prim_rev(
-    Grid g, Tiling tl, Box bx, const float* __restrict__ E0, const float* __restrict__ H0, float* __restrict__ E1,
-    float* __restrict__ H1, const float* __restrict__ eps, float* __restrict__ Eb0, const void* __restrict__ store,
-    Interp qE, Interp qH, int inject_h, float wave, double* __restrict__ grad) {
+    Grid g, Tiling tl, Box bx, const float* __restrict__ F0, float* __restrict__ F1, const float* __restrict__ eps,
+    float* __restrict__ Eb0, float wave, double* __restrict__ grad) {
     __shared__ float sH[2][3][TY + 2][EXT];       // H^{n+1/2}, extended planes
     __shared__ float sE[2][3][TY + 1][TX + 1];     // E^n on the tile plus the +x column / +y row
     const int L = logical_tile(tl.count);
     const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
     RevCtx<TY> c;
-    c.i0 = bx.o[0] + tix * TX;
+    c.i0 = bx.tx0 + tix * TX;
     c.j0 = bx.o[1] + tiy * TY;
     const int k0 = bx.o[2] + tiz * CZ;
     const int k1 = min(k0 + CZ, bx.o[2] + bx.n[2]);
@@ -485,17 +495,15 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     const int lane = c.lane, row = c.row, tid = row * TX + lane;
     c.x = c.i0 + lane;
     c.y = c.j0 + row;
-    c.live = c.x < bx.o[0] + bx.n[0] && c.y < bx.o[1] + bx.n[1];
+    c.live = c.x >= bx.o[0] && c.x < bx.o[0] + bx.n[0] && c.y < bx.o[1] + bx.n[1];
     c.N = (int)g.N;
     c.plane = g.nx * g.ny;
     const int N = c.N, P = g.P;
+    const uint32_t nb = (uint32_t)N << 2;
     const float dt = g.dt;
     RevBufs b;
-    const uint32_t fbytes = (uint32_t)(3 * N) * 4u;
-    b.E0 = make_rsrc(E0, fbytes);
-    b.H0 = make_rsrc(H0, fbytes);
-    b.E1 = make_rsrc(E1, fbytes);
-    b.H1 = make_rsrc(H1, fbytes);
+    b.F0 = make_rsrc(F0, (uint32_t)(6 * N) * 4u);
+    b.F1 = make_rsrc(F1, (uint32_t)(6 * N) * 4u);
     b.eps = make_rsrc(eps, (uint32_t)N * 4u);
     b.src = make_rsrc(g.src_profile, (uint32_t)((g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1]) *
                                                 (g.src_hi[2] - g.src_lo[2])) * 4u);
@@ -514,19 +522,49 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     if (tid < TY + 1) { c.pex = TX; c.pey = tid; }
     else if (tid < TY + 1 + TX) { c.pex = tid - TY - 1; c.pey = TY; }
     if (c.pex >= 0) c.xcol = make_col(g, c.i0 + c.pex, c.j0 + c.pey);
+    RevLanes Ln;
+    Ln.h = lane_off(c.own.xy >= 0, c.own.xy);
+    Ln.r = lane_off(c.ring.xy >= 0, c.ring.xy);
+    Ln.e = lane_off(xy_interior(g, c.own), c.own.xy);
+    Ln.xe = lane_off(xy_interior(g, c.xcol), c.xcol.xy);
+    Ln.src = src_lane(g, c.own);
+    Ln.xsrc = src_lane(g, c.xcol);
+    Ln.st = lane_off(c.live && xy_interior(g, c.own), c.own.xy);
+    {
+        auto shell = [&](const Col& q, uint32_t& k_off, uint32_t& z_off) {
+            const bool iI = q.x >= P && q.x < g.nx - P, jI = q.y >= P && q.y < g.ny - P;
+            const bool fk = P > 0 && q.xy >= 0 && ((q.x == g.nx - P && jI) || (q.y == g.ny - P && iI));
+            k_off = lane_off(fk, q.xy);
+            z_off = lane_off(P > 0 && q.xy >= 0 && iI && jI, q.xy);
+        };
+        shell(c.own, Ln.shk, Ln.shz);
+        shell(c.xcol, Ln.xshk, Ln.xshz);
+    }
 
     // prologue: H^{n+1/2} planes k0-1 and k0 into LDS, then E^n at k0
     RevIn pin[2];
     {
         const int zm = bound(k0 - 1, g.nz, g.periodic), z0 = bound(k0, g.nz, g.periodic);
-        float hm[3], rhm[3], h0[3], rh0[3], e1[3], xe1[3], ep, xep, sp, xsp;
-        bld3(b.H0, (c.own.xy < 0 || zm < 0) ? -1 : c.own.xy + zm * c.plane, N, hm);
-        bld3(b.H0, (c.ring.xy < 0 || zm < 0) ? -1 : c.ring.xy + zm * c.plane, N, rhm);
-        bld3(b.H0, (c.own.xy < 0 || z0 < 0) ? -1 : c.own.xy + z0 * c.plane, N, h0);
-        bld3(b.H0, (c.ring.xy < 0 || z0 < 0) ? -1 : c.ring.xy + z0 * c.plane, N, rh0);
-        load_e_in(g, b, c.own, z0, c.plane, e1, ep, sp);
-        load_e_in(g, b, c.xcol, z0, c.plane, xe1, xep, xsp);
-        load_rev_in<TY>(g, b, c, k0, pin[0]);
+        const uint32_t sm = uni(zm < 0 ? 0u : (uint32_t)(zm * c.plane) << 2), s0 = uni((uint32_t)(z0 * c.plane) << 2);
+        float hm[3], rhm[3], h0[3], rh0[3], e1[3], xe1[3];
+        bld3v(b.F0, zm < 0 ? OOB : Ln.h, sm + 3 * nb, nb, hm);
+        bld3v(b.F0, zm < 0 ? OOB : Ln.r, sm + 3 * nb, nb, rhm);
+        bld3v(b.F0, Ln.h, s0 + 3 * nb, nb, h0);
+        bld3v(b.F0, Ln.r, s0 + 3 * nb, nb, rh0);
+        const bool zi = z_interior(g, z0);
+        bld3v(b.F0, zi ? Ln.e : OOB, s0, nb, e1);
+        bld3v(b.F0, zi ? Ln.xe : OOB, s0, nb, xe1);
+        float ep = bldv(b.eps, zi ? Ln.e : OOB, s0), xep = bldv(b.eps, zi ? Ln.xe : OOB, s0);
+        uint32_t ss;
+        const bool sz = src_z(g, z0, ss);
+        const float sp = bldv(b.src, sz ? Ln.src : OOB, ss), xsp = bldv(b.src, sz ? Ln.xsrc : OOB, ss);
+        const bool zh = z0 == g.nz - P;
+        float sh[3], xsh[3];
+        bld3v(b.F1, zi ? Ln.shk : (zh ? Ln.shz : OOB), s0, nb, sh);
+        bld3v(b.F1, zi ? Ln.xshk : (zh ? Ln.xshz : OOB), s0, nb, xsh);
+        load_rev_in<TY>(g, b, Ln, c, k0, pin[0]);
+        ep = ep == 0.0f ? 1.0f : ep;
+        xep = xep == 0.0f ? 1.0f : xep;
         #pragma unroll
         for (int q = 0; q < 3; ++q) {
             sH[0][q][row + 1][lane + 1] = hm[q];
@@ -537,14 +575,13 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
             for (int q = 0; q < 3; ++q) { sH[0][q][c.rly][c.rlx] = rhm[q]; sH[1][q][c.rly][c.rlx] = rh0[q]; }
         }
         __syncthreads();
-        e_plane<TY, DT>(g, b, c, sE[0], sH[1], sH[0], z0, true, e1, ep, sp, xe1, xep, xsp, wave, store, qE, Eb0,
-                        grad);
+        e_plane<TY>(g, b, Ln, c, sE[0], sH[1], sH[0], z0, true, e1, ep, sp, sh, xe1, xep, xsp, xsh, wave, Eb0, grad);
     }
     __syncthreads();   // the first plane overwrites sH[0], which the prologue has just read
     #pragma unroll
     for (int kk = 0; kk < CZ; ++kk) {
         const int k = k0 + kk;
-        if (kk + 1 < CZ) load_rev_in<TY>(g, b, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+        if (kk + 1 < CZ) load_rev_in<TY>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
         if (k >= k1) continue;
         const int hc = (kk + 1) & 1, hn = 1 - hc;      // H plane k in sH[hc]
         const int ec = kk & 1, en = 1 - ec;            // E^n plane k in sE[ec]
@@ -558,13 +595,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
         __syncthreads();
         // E^n at plane k+1 (own cell, and the +x column / +y row)
         const int z1 = bound(k + 1, g.nz, g.periodic);
-        e_plane<TY, DT>(g, b, c, sE[en], sH[hn], sH[hc], z1, k + 1 < k1, in.e, in.ep, in.sp, in.xe, in.xep, in.xsp,
-                        wave, store, qE, Eb0, grad);
+        e_plane<TY>(g, b, Ln, c, sE[en], sH[hn], sH[hc], z1, k + 1 < k1, in.e, in.ep, in.sp, in.sh, in.xe, in.xep,
+                    in.xsp, in.xsh, wave, Eb0, grad);
         __syncthreads();
-        // H^{n-1/2} at plane k on the tile
-        const bool iI = c.x >= P && c.x < g.nx - P, jI = c.y >= P && c.y < g.ny - P, kI = k >= P && k < g.nz - P;
-        const bool hint = c.live && iI && jI && kI;
-        const int idx = hint ? c.own.xy + k * c.plane : -1;
+        // H^{n-1/2} at plane k on the tile (interior cells; lane offset OOB elsewhere)
+        const bool kI = z_interior(g, k);
         float h[3];
         {
             const float exc = sE[ec][0][row][lane], eyc = sE[ec][1][row][lane], ezc = sE[ec][2][row][lane];
@@ -572,53 +607,42 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
             h[1] = sH[hc][1][row + 1][lane + 1] + dt * ((sE[en][0][row][lane] - exc) - (sE[ec][2][row][lane + 1] - ezc));
             h[2] = sH[hc][2][row + 1][lane + 1] + dt * ((sE[ec][1][row][lane + 1] - eyc) - (sE[ec][0][row + 1][lane] - exc));
         }
-        bst3(b.H1, idx, N, h);
-        if (inject_h && P > 0 && c.live && !hint) {
-            // H^{n-1/2} on the low interface faces, for the next reverse step (rare)
-            const int x = c.x, y = c.y;
-            const int gi = c.own.xy + k * c.plane;
-            if (x == P - 1 && jI && kI) {
-                const int o = (k - P) * g.my + (y - P);
-                H1[N + gi] = shell_value_t<DT>(g, store, qH, 0, o);
-                H1[2 * N + gi] = shell_value_t<DT>(g, store, qH, 1, o);
-            } else if (y == P - 1 && iI && kI) {
-                const int o = (k - P) * g.mx + (x - P);
-                H1[2 * N + gi] = shell_value_t<DT>(g, store, qH, 2, o);
-                H1[gi] = shell_value_t<DT>(g, store, qH, 3, o);
-            } else if (k == P - 1 && iI && jI) {
-                const int o = (y - P) * g.mx + (x - P);
-                H1[gi] = shell_value_t<DT>(g, store, qH, 4, o);
-                H1[N + gi] = shell_value_t<DT>(g, store, qH, 5, o);
-            }
-        }
+        bst3v(b.F1, kI ? Ln.st : OOB, uni(((uint32_t)(k * c.plane) << 2) + 3 * nb), nb, h);
     }
 }
 
-// The recorded low-face H of the last step, injected into the final forward state.
-__global__ __launch_bounds__(256) void k_inject_h(Grid g, float* __restrict__ H, const void* __restrict__ store,
-                                                  Interp q) {
+// The interface shell of one reverse step written into a field buffer F (E then H)
+// from the store: H at the low faces (blocks 0-5, interpolation qH) when do_h, E at
+// the high faces (blocks 6-11, interpolation qE) when do_e.  One thread per face cell
+// and side; the first ax+ay+az threads take the low faces.
+template <int DT>
+__global__ __launch_bounds__(256) void k_inject_shell(Grid g, float* __restrict__ F, const void* __restrict__ store,
+                                                      Interp qE, Interp qH, int do_e, int do_h) {
     const int P = g.P;
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long ax = (long long)g.my * g.mz, ay = (long long)g.mx * g.mz, az = (long long)g.mx * g.my;
+    const long long face = ax + ay + az;
+    long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool high = t >= face;
+    if (high) t -= face;
+    if (t >= face || (high ? !do_e : !do_h)) return;
     const int N = (int)g.N;
+    float* A = F + (high ? 0 : 3 * (long long)N);           // E for the high faces, H for the low ones
+    const Interp& q = high ? qE : qH;
+    const int b0 = high ? 6 : 0;
+    int x, y, z, c0, c1, blk;
+    long long u;
     if (t < ax) {
-        const int y = P + (int)(t % g.my), z = P + (int)(t / g.my), x = P - 1;
-        const int idx = x + g.nx * (y + g.ny * z);
-        H[N + idx] = shell_value(g, store, q, 0, t);
-        H[2 * N + idx] = shell_value(g, store, q, 1, t);
+        u = t; blk = b0; y = P + (int)(u % g.my); z = P + (int)(u / g.my); x = high ? g.nx - P : P - 1; c0 = 1; c1 = 2;
     } else if (t < ax + ay) {
-        const long long u = t - ax;
-        const int x = P + (int)(u % g.mx), z = P + (int)(u / g.mx), y = P - 1;
-        const int idx = x + g.nx * (y + g.ny * z);
-        H[2 * N + idx] = shell_value(g, store, q, 2, u);
-        H[idx] = shell_value(g, store, q, 3, u);
-    } else if (t < ax + ay + az) {
-        const long long u = t - ax - ay;
-        const int x = P + (int)(u % g.mx), y = P + (int)(u / g.mx), z = P - 1;
-        const int idx = x + g.nx * (y + g.ny * z);
-        H[idx] = shell_value(g, store, q, 4, u);
-        H[N + idx] = shell_value(g, store, q, 5, u);
+        u = t - ax; blk = b0 + 2; x = P + (int)(u % g.mx); z = P + (int)(u / g.mx); y = high ? g.ny - P : P - 1;
+        c0 = 2; c1 = 0;
+    } else {
+        u = t - ax - ay; blk = b0 + 4; x = P + (int)(u % g.mx); y = P + (int)(u / g.mx); z = high ? g.nz - P : P - 1;
+        c0 = 0; c1 = 1;
     }
+    const int idx = x + g.nx * (y + g.ny * z);
+    A[c0 * N + idx] = shell_value_t<DT>(g, store, q, blk, u);
+    A[c1 * N + idx] = shell_value_t<DT>(g, store, q, blk + 1, u);
 }
 
 __global__ void k_scale_grad(double* g, long long n, const double* s) {
@@ -642,34 +666,32 @@ void launch_adj_step(const Grid& g, const Tiling& t, const float* Eb0, const flo
 }
 
 template <int TY, int CZ>
-static void launch_prim_rev_t(const Grid& g, const Tiling& t, const Box& b, const float* E0, const float* H0,
-                              float* E1, float* H1, const float* eps, float* Eb0, const void* store, Interp qE,
-                              Interp qH, int inject_h, float wave, double* grad, hipStream_t s) {
-    with_dtype(g.dtype, [&]<int DT>() {
-        launch_kernel(K_PRIM_REV, k_prim_rev<TY, DT, CZ>, dim3(t.count), dim3(TX, TY), s, g, t, b, E0, H0, E1, H1,
-                      eps, Eb0, store, qE, qH, inject_h, wave, grad);
-    });
+static void launch_prim_rev_t(const Grid& g, const Tiling& t, const Box& b, const float* F0, float* F1,
+                              const float* eps, float* Eb0, float wave, double* grad, hipStream_t s) {
+    launch_kernel(K_PRIM_REV, k_prim_rev<TY, CZ>, dim3(t.count), dim3(TX, TY), s, g, t, b, F0, F1, eps, Eb0, wave,
+                  grad);
 }
 
-void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], const float* E0,
-                     const float* H0, float* E1, float* H1, const float* eps, float* Eb0, const void* store,
-                     Interp qE, Interp qH, int inject_h, float wave, double* grad, hipStream_t s) {
+void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
+                     const float* F0, float* F1, const float* eps, float* Eb0, float wave, double* grad,
+                     hipStream_t s) {
     Box b;
     for (int d = 0; d < 3; ++d) { b.o[d] = box_o[d]; b.n[d] = box_n[d]; }
-    if (t.ty == 4 && t.cz == 4)
-        launch_prim_rev_t<4, 4>(g, t, b, E0, H0, E1, H1, eps, Eb0, store, qE, qH, inject_h, wave, grad, s);
-    else if (t.ty == 4)
-        launch_prim_rev_t<4, 8>(g, t, b, E0, H0, E1, H1, eps, Eb0, store, qE, qH, inject_h, wave, grad, s);
-    else if (t.cz == 4)
-        launch_prim_rev_t<8, 4>(g, t, b, E0, H0, E1, H1, eps, Eb0, store, qE, qH, inject_h, wave, grad, s);
-    else
-        launch_prim_rev_t<8, 8>(g, t, b, E0, H0, E1, H1, eps, Eb0, store, qE, qH, inject_h, wave, grad, s);
+    b.tx0 = tile_x0;
+    if (t.ty == 4 && t.cz == 4) launch_prim_rev_t<4, 4>(g, t, b, F0, F1, eps, Eb0, wave, grad, s);
+    else if (t.ty == 4) launch_prim_rev_t<4, 8>(g, t, b, F0, F1, eps, Eb0, wave, grad, s);
+    else if (t.cz == 4) launch_prim_rev_t<8, 4>(g, t, b, F0, F1, eps, Eb0, wave, grad, s);
+    else launch_prim_rev_t<8, 8>(g, t, b, F0, F1, eps, Eb0, wave, grad, s);
 }
 
-void launch_inject_h(const Grid& g, float* H, const void* store, Interp q, hipStream_t s) {
-    if (g.P == 0) return;
-    const long long n = (long long)g.my * g.mz + (long long)g.mx * g.mz + (long long)g.mx * g.my;
-    launch_kernel(K_INJECT, k_inject_h, dim3((unsigned)((n + 255) / 256)), dim3(256), s, g, H, store, q);
+void launch_inject_shell(const Grid& g, float* F, const void* store, Interp qE, Interp qH, int do_e, int do_h,
+                         hipStream_t s) {
+    if (g.P == 0 || (!do_e && !do_h)) return;
+    const long long n = 2 * ((long long)g.my * g.mz + (long long)g.mx * g.mz + (long long)g.mx * g.my);
+    with_dtype(g.dtype, [&]<int DT>() {
+        launch_kernel(K_INJECT, k_inject_shell<DT>, dim3((unsigned)((n + 255) / 256)), dim3(256), s, g, F, store, qE,
+                      qH, do_e, do_h);
+    });
 }
 
 void launch_scale_grad(double* grad, long long n, const double* scale, hipStream_t s) {
