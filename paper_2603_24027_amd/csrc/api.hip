@@ -447,7 +447,6 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
     const int64_t N = g.N;
     float* Fp[2] = {fields, (float*)(ws + pl.ws_fields)};                       // primal
     float* Fa[2] = {adj_fields, (float*)(ws + pl.ws_fields + pl.info.fields_bytes)};   // adjoint
-    float* psi_buf[2] = {adj_psi, adj_psi + pl.psi_floats};
     const float* wave = prob->src_wave;
     auto enqueue = [&](hipStream_t q) {
         launch_fill(Fa[0], 6 * N, 0.0f, q);
@@ -466,8 +465,7 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
             launch_inject_shell(g, pn, store, interp_for(n, T, k), n >= 1 ? interp_for(n - 1, T, k) : none, 1, n >= 1,
                                 q);
             launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], grad_eps, q);
-            launch_adj_step(g, pl.fwd, ao, ao + 3 * N, an, an + 3 * N, eps, psi_buf[st & 1],
-                            psi_buf[(st + 1) & 1], q);
+            launch_adj_step(g, pl.fwd, ao, an, eps, adj_psi, st & 1, q);
         }
         if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, q);
     };

@@ -438,8 +438,8 @@ void launch_inject_shell(const Grid& g, float* F, const void* store, Interp qE, 
 void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
                      const float* F0, float* F1, const float* eps, float* Eb0, float wave, double* grad,
                      hipStream_t s);
-void launch_adj_step(const Grid& g, const Tiling& t, const float* Eb0, const float* Hb0, float* Eb1, float* Hb1,
-                     const float* eps, const float* psi_in, float* psi_out, hipStream_t s);
+void launch_adj_step(const Grid& g, const Tiling& t, const float* A0, float* A1, const float* eps, float* psi,
+                     int pcopy, hipStream_t s);
 void launch_scale_grad(double* grad, long long n, const double* scale, hipStream_t s);
 void launch_codec_roundtrip(int dtype, const float* values, long long n_blocks, long long block_len,
                             void* codes, float* scales, float* decoded, hipStream_t s);

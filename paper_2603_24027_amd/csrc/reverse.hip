@@ -64,7 +64,17 @@ __device__ inline void hbar_new(const float (*cur)[TY + 2][EXT], const float (*n
 }
 
 struct AdjBufs {
-    rsrc_t Eb0, Hb0, Eb1, Hb1, eps, pin, pout;
+    rsrc_t A0, A1, eps, psi;   // adjoint fields in / out (Ebar then Hbar), both PML copies
+    uint32_t pin, pout;        // byte offsets of the PML copies in / out
+};
+
+// Loop-invariant per-lane byte offsets of the adjoint sweep: Ebar/eps of the own column
+// (boundary rule) and of the ring position, the own cell (live lanes), the halo cell,
+// and the PML auxiliaries of the own column (boundary rule and live), ring and halo.
+struct AdjLanes {
+    uint32_t eo, er, o, hc;
+    PsiLane pg, po, pr, ph;
+    bool ysl;                 // the own row lies in a y slab (uniform across a wave)
 };
 
 // What the adjoint sweep reads from memory for plane k of its column, loaded
@@ -78,34 +88,34 @@ struct AdjIn {
     float hhb[3], phh[6];
 };
 
-// Ebar, eps and E-side auxiliaries of column c on plane z (z < 0: outside, all 0, eps 1).
-__device__ __forceinline__ void load_ge_in(const Grid& g, const AdjBufs& b, const Col& c, int z, int plane,
-                                           float eb[3], float& ep, float pe[6]) {
-    const int idx = (c.xy < 0 || z < 0) ? -1 : c.xy + z * plane;
-    bld3(b.Eb0, idx, (int)g.N, eb);
-    const float e = bld(b.eps, idx < 0 ? OOB : (uint32_t)idx << 2);
-    ep = idx < 0 ? 1.0f : e;
-    int po[3];
-    psi_offsets(g, c, z, (idx >= 0 && g.P > 0) ? slab_coord(z, g.nz, g.P) : -1, 1, po);
-    if (idx < 0) po[0] = po[1] = po[2] = -1;
-    bld_psi(g, b.pin, po, pe);
+// Ebar, eps and E-side auxiliaries at the lane offsets (v, pl) on plane z (z < 0: 0, eps 1).
+__device__ __forceinline__ void load_ge_in(const Grid& g, const AdjBufs& b, uint32_t v, const PsiLane& pl, int z,
+                                           int plane, uint32_t nb, float eb[3], float& ep, float pe[6]) {
+    const uint32_t s = uni(z < 0 ? 0u : (uint32_t)(z * plane) << 2);
+    const uint32_t vv = z < 0 ? OOB : v;
+    bld3v(b.A0, vv, s, nb, eb);
+    const float e = bldv(b.eps, vv, s);
+    ep = e == 0.0f ? 1.0f : e;          // outside the domain eps reads 0
+    PsiPlane pp = psi_plane(g, 1, z < 0 ? 0 : z, b.pin);
+    pp.zs = pp.zs && z >= 0;
+    PsiLane l = pl;
+    if (z < 0) l.x = l.y = l.z = OOB;
+    bld_psi_v(b.psi, l, pp, pe);
 }
 
 template <int TY>
-__device__ __forceinline__ void load_adj_in(const Grid& g, const AdjBufs& b, const FwdCtx<TY>& c, int k, AdjIn& d) {
+__device__ __forceinline__ void load_adj_in(const Grid& g, const AdjBufs& b, const AdjLanes& L, const FwdCtx<TY>& c,
+                                            int k, AdjIn& d) {
+    const uint32_t nb = (uint32_t)c.N << 2;
     const int z1 = bound(k + 1, g.nz, g.periodic);
-    load_ge_in(g, b, c.own, z1, c.plane, d.eb, d.ep, d.pe);
-    load_ge_in(g, b, c.ring, z1, c.plane, d.rb, d.rep, d.rpe);
-    const int ok = k * c.plane;
-    const int szk = g.P > 0 ? slab_coord(k, g.nz, g.P) : -1;
-    bld3(b.Hb0, c.live ? c.own.xy + ok : -1, c.N, d.hb);
-    bld3(b.Hb0, c.hc.xy >= 0 ? c.hc.xy + ok : -1, c.N, d.hhb);
-    int po[3];
-    psi_offsets(g, c.own, k, c.live ? szk : -1, 0, po);
-    if (!c.live) po[0] = po[1] = -1;
-    bld_psi(g, b.pin, po, d.ph);
-    psi_offsets(g, c.hc, k, szk, 0, po);
-    bld_psi(g, b.pin, po, d.phh);
+    load_ge_in(g, b, L.eo, L.pg, z1, c.plane, nb, d.eb, d.ep, d.pe);
+    load_ge_in(g, b, L.er, L.pr, z1, c.plane, nb, d.rb, d.rep, d.rpe);
+    const uint32_t sk = uni(((uint32_t)(k * c.plane) << 2) + 3 * nb);
+    bld3v(b.A0, L.o, sk, nb, d.hb);
+    bld3v(b.A0, L.hc, sk, nb, d.hhb);
+    const PsiPlane pH = psi_plane(g, 0, k, b.pin);
+    bld_psi_v(b.psi, L.po, pH, d.ph);
+    bld_psi_v(b.psi, L.ph, pH, d.phh);
 }
 
 // E-half gbar at one position from its inputs: v = (dt/eps) Ebar, raw terms
@@ -118,29 +128,55 @@ __device__ __forceinline__ void ge_terms(float dt, const float eb[3], float ep, 
     gbar_apply(cx, cy, cz, o, pe, pout);
 }
 
+// Transpose of one axis' CPML on its two terms (x: 3, 4; y: 0, 5; z: 1, 2):
+// q = psibar + o, o <- kinv o + a q, new psibar = b q.
+__device__ inline void gbar_axis(const Cf& c, int i, int j, float o[6], const float pin[6], float pout[6]) {
+    float q = pin[i] + o[i];
+    o[i] = c.k * o[i] + c.a * q;
+    pout[i] = c.b * q;
+    q = pin[j] + o[j];
+    o[j] = c.k * o[j] + c.a * q;
+    pout[j] = c.b * q;
+}
+
+// E-half gbar of the own cell at plane k+1 (y and z parts under uniform branches).
+template <int TY, int CZ>
+__device__ __forceinline__ void ge_own(float dt, const CoefTile<TY, CZ>& ct, int lx, int ly, int lz, bool ysl,
+                                       bool zsl, const float eb[3], float ep, const float pe[6], float o[6],
+                                       float po[6]) {
+    const float cc = dt_over_eps(dt, ep);
+    const float vx = cc * eb[0], vy = cc * eb[1], vz = cc * eb[2];
+    o[0] = vx; o[1] = -vx; o[2] = vy; o[3] = -vy; o[4] = vz; o[5] = -vz;
+    po[0] = po[1] = po[2] = po[5] = 0.0f;
+    gbar_axis(cf_x(ct, 0, lx), 3, 4, o, pe, po);
+    if (ysl) gbar_axis(cf_y(ct, 0, ly), 0, 5, o, pe, po);
+    if (zsl) gbar_axis(cf_z(ct, 0, lz), 1, 2, o, pe, po);
+}
+
 // One plane k of the adjoint sweep: E-half gbar of plane k+1 (own cell and ring
 // position) into LDS, the H-half transpose on the own and halo cells of plane k,
 // then Ebar of the own cell at plane k.
 template <int TY, int CZ>
-__device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const FwdCtx<TY>& c,
+__device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const AdjLanes& L, const FwdCtx<TY>& c,
                                           float (*sG)[6][TY + 2][EXT], float (*sGH)[TY + 1][TX + 1],
                                           const CoefTile<TY, CZ>& ct, int kk, int k, bool own_next, int cur,
                                           const AdjIn& in, float ebc[3], float& g1p, float& g2p) {
     const int nxt = 1 - cur;
-    const int N = c.N, row = c.row, lane = c.lane;
+    const int row = c.row, lane = c.lane;
+    const uint32_t nb = (uint32_t)c.N << 2;
     const float dt = g.dt;
     const int z1 = bound(k + 1, g.nz, g.periodic);
     // ---- E-half gbar of plane k+1 ----
     {
+        PsiPlane pp = psi_plane(g, 1, z1 < 0 ? 0 : z1, b.pout);
+        pp.zs = pp.zs && z1 >= 0;
         float o[6], po[6];
-        ge_terms(dt, in.eb, in.ep, in.pe, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, kk + 2), o, po);
+        ge_own<TY, CZ>(dt, ct, lane + 1, row + 1, kk + 2, L.ysl, pp.zs, in.eb, in.ep, in.pe, o, po);
         #pragma unroll
         for (int t = 0; t < 6; ++t) sG[nxt][t][row + 1][lane + 1] = o[t];
-        int off[3];
-        const bool w = c.live && own_next && z1 >= 0;
-        psi_offsets(g, c.own, z1, (w && g.P > 0) ? slab_coord(z1, g.nz, g.P) : -1, 1, off);
-        if (!w) off[0] = off[1] = off[2] = -1;
-        bst_psi(g, b.pout, off, po);
+        PsiLane l = L.po;                        // the block's own cells at k+1 only
+        if (!own_next || z1 < 0) l.x = l.y = l.z = OOB;
+        bst_psi_v(b.psi, l, pp, po);
         if (c.rlx >= 0) {
             ge_terms(dt, in.rb, in.rep, in.rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, kk + 2), o, po);
             #pragma unroll
@@ -149,22 +185,20 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
     }
     __syncthreads();
     // ---- H-half transpose at plane k: own cell (stored) and halo cell (LDS only) ----
-    const int ok = k * c.plane;
-    const int szk = g.P > 0 ? slab_coord(k, g.nz, g.P) : -1;
-    const int idx = c.live ? c.own.xy + ok : -1;
+    const uint32_t sk = uni((uint32_t)(k * c.plane) << 2);
+    const PsiPlane pH = psi_plane(g, 0, k, b.pout);
     float og[6];
     {
-        float h[3], po[6];
+        float h[3], po[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         hbar_new<TY>(sG[cur], sG[nxt], lane + 1, row + 1, in.hb, h);
-        bst3(b.Hb1, idx, N, h);
+        bst3v(b.A1, L.o, sk + 3 * nb, nb, h);
         og[0] = -dt * h[0]; og[1] = dt * h[0]; og[2] = -dt * h[1]; og[3] = dt * h[1]; og[4] = -dt * h[2];
         og[5] = dt * h[2];
-        gbar_apply(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, kk + 1), og, in.ph, po);
+        gbar_axis(cf_x(ct, 1, lane + 1), 3, 4, og, in.ph, po);
+        if (L.ysl) gbar_axis(cf_y(ct, 1, row + 1), 0, 5, og, in.ph, po);
+        if (pH.zs) gbar_axis(cf_z(ct, 1, kk + 1), 1, 2, og, in.ph, po);
         if (!c.live) og[0] = og[1] = og[2] = og[3] = og[4] = og[5] = 0.0f;
-        int off[3];
-        psi_offsets(g, c.own, k, c.live ? szk : -1, 0, off);
-        if (!c.live) off[0] = off[1] = -1;
-        bst_psi(g, b.pout, off, po);
+        bst_psi_v(b.psi, L.po, pH, po);
         #pragma unroll
         for (int t = 0; t < 6; ++t) sGH[t][row + 1][lane + 1] = og[t];
     }
@@ -186,23 +220,23 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
     e[0] = ebc[0] + (g2p - og[2]) + (sGH[5][row][lane + 1] - og[5]);
     e[1] = ebc[1] + (g1p - og[1]) + (sGH[4][row + 1][lane] - og[4]);
     e[2] = ebc[2] + (sGH[0][row][lane + 1] - og[0]) + (sGH[3][row + 1][lane] - og[3]);
-    bst3(b.Eb1, idx, N, e);
+    bst3v(b.A1, L.o, sk, nb, e);
     g1p = og[1];
     g2p = og[2];
     ebc[0] = in.eb[0]; ebc[1] = in.eb[1]; ebc[2] = in.eb[2];
 }
 
-// One adjoint step: (Ebar, Hbar, psibar) in Eb0/Hb0/psi_in -> Eb1/Hb1/psi_out.
-// Ebar already carries this step's loss seed (added by the primal reversal).
-// Unrolled over the CZ planes and software-pipelined like the forward sweep.
+// One adjoint step: (Ebar, Hbar) in A0 and the auxiliaries in PML copy `pcopy` ->
+// A1 and copy 1 - pcopy.  Ebar already carries this step's loss seed (added by the
+// primal reversal).  Unrolled over the CZ planes and software-pipelined like the
+// forward sweep.
 #ifndef FDTD_ADJ_WAVES
 #define FDTD_ADJ_WAVES 1
 #endif
 template <int TY, int CZ>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_ADJ_WAVES))) void k_adj_step(
-    Grid g, Tiling tl, const float* __restrict__ Eb0, const float* __restrict__ Hb0, float* __restrict__ Eb1,
-    float* __restrict__ Hb1, const float* __restrict__ eps, const float* __restrict__ psi_in,
-    float* __restrict__ psi_out) {
+    Grid g, Tiling tl, const float* __restrict__ A0, float* __restrict__ A1, const float* __restrict__ eps,
+    float* __restrict__ psi, int pcopy) {
     __shared__ float sG[2][6][TY + 2][EXT];
     __shared__ float sGH[6][TY + 1][TX + 1];
     __shared__ CoefTile<TY, CZ> ct;
@@ -223,20 +257,21 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
     c.P = g.P;
     c.plane = g.nx * g.ny;
     const int lane = c.lane, row = c.row;
+    const uint32_t nb = (uint32_t)c.N << 2;
     const float dt = g.dt;
     AdjBufs b;
-    const uint32_t fbytes = (uint32_t)(3 * c.N) * 4u, psib = (uint32_t)g.psi_total * 4u;
-    b.Eb0 = make_rsrc(Eb0, fbytes);
-    b.Hb0 = make_rsrc(Hb0, fbytes);
-    b.Eb1 = make_rsrc(Eb1, fbytes);
-    b.Hb1 = make_rsrc(Hb1, fbytes);
+    const uint32_t psib = (uint32_t)g.psi_total * 4u;
+    b.A0 = make_rsrc(A0, (uint32_t)(6 * c.N) * 4u);
+    b.A1 = make_rsrc(A1, (uint32_t)(6 * c.N) * 4u);
     b.eps = make_rsrc(eps, (uint32_t)c.N * 4u);
-    b.pin = make_rsrc(psi_in, psib);
-    b.pout = make_rsrc(psi_out, psib);
+    b.psi = make_rsrc(psi, 2 * psib);
+    b.pin = pcopy ? psib : 0u;
+    b.pout = pcopy ? 0u : psib;
 
     c.own = make_col(g, c.x, c.y);
     c.rlx = c.rly = -1;
     c.ring.xy = -1;
+    c.ring.x = c.ring.y = 0;
     c.ring.sx = c.ring.sy = -1;
     if (row == 0) { c.rlx = lane + 1; c.rly = 0; c.ring = make_col(g, c.i0 + lane, c.j0 - 1); }
     else if (row == 1) { c.rlx = lane + 1; c.rly = TY + 1; c.ring = make_col(g, c.i0 + lane, c.j0 + TY); }
@@ -244,13 +279,25 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
     else if (row == 3 && lane < TY + 2) { c.rlx = EXT - 1; c.rly = lane; c.ring = make_col(g, c.i0 + TX, c.j0 - 1 + lane); }
     c.hex = c.hey = -1;
     c.hc.xy = -1;
+    c.hc.x = c.hc.y = 0;
     c.hc.sx = c.hc.sy = -1;
     if (c.tid < TX + TY) {
         if (c.tid < TX) { c.hex = c.tid + 1; c.hey = 0; } else { c.hex = 0; c.hey = c.tid - TX + 1; }
         const int xr = c.i0 - 1 + c.hex, yr = c.j0 - 1 + c.hey;
         if (xr < g.nx && yr < g.ny) c.hc = make_col(g, xr, yr);
     }
-    fill_coef_tile<TY, CZ>(g, ct, c.i0, c.j0, k0, c.tid, TX * TY);   // published by the prologue's barrier
+    AdjLanes Ln;
+    Ln.eo = lane_off(c.own.xy >= 0, c.own.xy);
+    Ln.er = lane_off(c.ring.xy >= 0, c.ring.xy);
+    Ln.o = lane_off(c.live, c.own.xy);
+    Ln.hc = lane_off(c.hc.xy >= 0, c.hc.xy);
+    Ln.pg = psi_lane(g, c.own, c.own.xy >= 0);
+    Ln.po = psi_lane(g, c.own, c.live);
+    Ln.pr = psi_lane(g, c.ring, c.ring.xy >= 0);
+    Ln.ph = psi_lane(g, c.hc, c.hc.xy >= 0);
+    Ln.ysl = c.own.sy >= 0;
+    fill_coef_tile<TY, CZ>(g, ct, c.i0, c.j0, k0, c.tid, TX * TY);
+    __syncthreads();   // the prologue's E-half terms read the coefficient tile
 
     // prologue: E-half gbar of planes k0-1 and k0, Ebar of the own cell at k0, and the
     // z-terms of the H-half gbar of the own cell at k0-1
@@ -261,17 +308,19 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
         const int zm = bound(k0 - 1, g.nz, g.periodic);
         const int z0 = bound(k0, g.nz, g.periodic);
         float eb[3], ep, pe[6], rb[3], rep, rpe[6], eb0[3], ep0, pe0[6], rb0[3], rep0, rpe0[6], hb[3], ph[6];
-        load_ge_in(g, b, c.own, zm, c.plane, eb, ep, pe);
-        load_ge_in(g, b, c.ring, zm, c.plane, rb, rep, rpe);
-        load_ge_in(g, b, c.own, z0, c.plane, eb0, ep0, pe0);
-        load_ge_in(g, b, c.ring, z0, c.plane, rb0, rep0, rpe0);
+        load_ge_in(g, b, Ln.eo, Ln.pg, zm, c.plane, nb, eb, ep, pe);
+        load_ge_in(g, b, Ln.er, Ln.pr, zm, c.plane, nb, rb, rep, rpe);
+        load_ge_in(g, b, Ln.eo, Ln.pg, z0, c.plane, nb, eb0, ep0, pe0);
+        load_ge_in(g, b, Ln.er, Ln.pr, z0, c.plane, nb, rb0, rep0, rpe0);
         const bool pro = c.live && zm >= 0;
-        bld3(b.Hb0, pro ? c.own.xy + zm * c.plane : -1, c.N, hb);
-        int off[3];
-        psi_offsets(g, c.own, zm, (pro && g.P > 0) ? slab_coord(zm, g.nz, g.P) : -1, 0, off);
-        if (!pro) off[0] = off[1] = -1;
-        bld_psi(g, b.pin, off, ph);
-        load_adj_in<TY>(g, b, c, k0, pin[0]);
+        const uint32_t sm = uni(zm < 0 ? 0u : ((uint32_t)(zm * c.plane) << 2) + 3 * nb);
+        bld3v(b.A0, zm < 0 ? OOB : Ln.o, sm, nb, hb);
+        PsiPlane pm = psi_plane(g, 0, zm < 0 ? 0 : zm, b.pin);
+        pm.zs = pm.zs && zm >= 0;
+        PsiLane lm = Ln.po;
+        if (zm < 0) lm.x = lm.y = lm.z = OOB;
+        bld_psi_v(b.psi, lm, pm, ph);
+        load_adj_in<TY>(g, b, Ln, c, k0, pin[0]);
         float o[6], po[6];
         ge_terms(dt, eb, ep, pe, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, 0), o, po);
         #pragma unroll
@@ -280,9 +329,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
         #pragma unroll
         for (int t = 0; t < 6; ++t) sG[1][t][row + 1][lane + 1] = o[t];
         // the own cell's E-side auxiliaries at k0 belong to this block
-        psi_offsets(g, c.own, z0, (c.live && g.P > 0) ? slab_coord(z0, g.nz, g.P) : -1, 1, off);
-        if (!c.live) off[0] = off[1] = off[2] = -1;
-        bst_psi(g, b.pout, off, po);
+        bst_psi_v(b.psi, Ln.po, psi_plane(g, 1, z0, b.pout), po);
         if (c.rlx >= 0) {
             ge_terms(dt, rb, rep, rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, 0), o, po);
             #pragma unroll
@@ -304,9 +351,9 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
     #pragma unroll
     for (int kk = 0; kk < CZ; ++kk) {
         const int k = k0 + kk;
-        if (kk + 1 < CZ) load_adj_in<TY>(g, b, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+        if (kk + 1 < CZ) load_adj_in<TY>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
         if (k < k1)
-            adj_plane<TY, CZ>(g, b, c, sG, sGH, ct, kk, k, k + 1 < k1, (kk + 1) & 1, pin[kk & 1], ebc, g1p, g2p);
+            adj_plane<TY, CZ>(g, b, Ln, c, sG, sGH, ct, kk, k, k + 1 < k1, (kk + 1) & 1, pin[kk & 1], ebc, g1p, g2p);
     }
 }
 
@@ -651,18 +698,17 @@ __global__ void k_scale_grad(double* g, long long n, const double* s) {
 }
 
 template <int TY, int CZ>
-static void launch_adj_t(const Grid& g, const Tiling& t, const float* Eb0, const float* Hb0, float* Eb1, float* Hb1,
-                         const float* eps, const float* psi_in, float* psi_out, hipStream_t s) {
-    launch_kernel(K_ADJ_STEP, k_adj_step<TY, CZ>, dim3(t.count), dim3(TX, TY), s, g, t, Eb0, Hb0, Eb1, Hb1, eps,
-                  psi_in, psi_out);
+static void launch_adj_t(const Grid& g, const Tiling& t, const float* A0, float* A1, const float* eps, float* psi,
+                         int pcopy, hipStream_t s) {
+    launch_kernel(K_ADJ_STEP, k_adj_step<TY, CZ>, dim3(t.count), dim3(TX, TY), s, g, t, A0, A1, eps, psi, pcopy);
 }
 
-void launch_adj_step(const Grid& g, const Tiling& t, const float* Eb0, const float* Hb0, float* Eb1, float* Hb1,
-                     const float* eps, const float* psi_in, float* psi_out, hipStream_t s) {
-    if (t.ty == 4 && t.cz == 4) launch_adj_t<4, 4>(g, t, Eb0, Hb0, Eb1, Hb1, eps, psi_in, psi_out, s);
-    else if (t.ty == 4) launch_adj_t<4, 8>(g, t, Eb0, Hb0, Eb1, Hb1, eps, psi_in, psi_out, s);
-    else if (t.cz == 4) launch_adj_t<8, 4>(g, t, Eb0, Hb0, Eb1, Hb1, eps, psi_in, psi_out, s);
-    else launch_adj_t<8, 8>(g, t, Eb0, Hb0, Eb1, Hb1, eps, psi_in, psi_out, s);
+void launch_adj_step(const Grid& g, const Tiling& t, const float* A0, float* A1, const float* eps, float* psi,
+                     int pcopy, hipStream_t s) {
+    if (t.ty == 4 && t.cz == 4) launch_adj_t<4, 4>(g, t, A0, A1, eps, psi, pcopy, s);
+    else if (t.ty == 4) launch_adj_t<4, 8>(g, t, A0, A1, eps, psi, pcopy, s);
+    else if (t.cz == 4) launch_adj_t<8, 4>(g, t, A0, A1, eps, psi, pcopy, s);
+    else launch_adj_t<8, 8>(g, t, A0, A1, eps, psi, pcopy, s);
 }
 
 template <int TY, int CZ>
