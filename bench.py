@@ -73,6 +73,22 @@ def algorithmic_bytes(prob, design_cells: int):
     }
 
 
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed counter summary of this kernel and workload
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or None when there is
+    none or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_pmc.txt" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("json: "):
+                rec = json.loads(line[len("json: "):])
+                if rec.get("kernel_source_hash") == kernel_source_hash():
+                    return rec.get("hbm_bytes_per_launch")
+    return None
+
+
 def oracle_baseline(prob_fn, sample_steps: int):
     """Time the FP64 oracle (as it stands) on the first steps of the workload's grid."""
     os.environ.setdefault("OMP_NUM_THREADS", "1")
@@ -235,13 +251,7 @@ def main():
                          "alg_bytes": ab[name], "GBps": ab[name] / avg_s / 1e9}
     dominant = max(kernels, key=lambda n: kernels[n]["avg_us"] * kernels[n]["launches"])
     dk = kernels[dominant]
-    traffic = None
-    pmc_path = os.path.join(ROOT, "profiles", "%s_%s_pmc.json" % (dominant, prob.name))
-    if os.path.exists(pmc_path):
-        with open(pmc_path) as f:
-            pmc = json.load(f)
-        if pmc.get("kernel_source_hash") == kernel_source_hash():
-            traffic = pmc.get("hbm_bytes_per_launch")
+    traffic = read_traffic(dominant, prob.name)
     roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(dk["GBps"], 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(dk["GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "alg_bytes_per_launch": ab[dominant], "avg_launch_us": round(dk["avg_us"], 2)}

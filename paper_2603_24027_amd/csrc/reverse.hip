@@ -570,7 +570,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     else if (tid < TY + 1 + TX) { c.pex = tid - TY - 1; c.pey = TY; }
     if (c.pex >= 0) c.xcol = make_col(g, c.i0 + c.pex, c.j0 + c.pey);
     RevLanes Ln;
-    Ln.h = lane_off(c.own.xy >= 0, c.own.xy);
+    // without wrap-around, idle lanes (outside the box) are never a neighbour of a box cell
+    Ln.h = lane_off(c.own.xy >= 0 && (c.live || g.periodic), c.own.xy);
     Ln.r = lane_off(c.ring.xy >= 0, c.ring.xy);
     Ln.e = lane_off(xy_interior(g, c.own), c.own.xy);
     Ln.xe = lane_off(xy_interior(g, c.xcol), c.xcol.xy);
