@@ -95,27 +95,29 @@ def oracle_baseline(prob_fn, sample_steps: int):
     from oracle import adjoint
     prob = prob_fn(steps=sample_steps)
     t0 = time.perf_counter()
-    adjoint.grad_time_reversal(prob, "fp32", 1, match_fp32=True)
+    adjoint.grad_time_reversal(prob, "fp64", 1)
     dt = time.perf_counter() - t0
     return prob.cells * sample_steps / dt / 1e6, dt, prob
 
 
-def oracle_grad_error(dtype_pairs):
-    """Gradient relative L2 error of the GPU path vs the FP64 oracle on the 32^3, 200-step case."""
-    import torch
-    import workloads as w
-    import paper_2603_24027_amd as pk
-    from oracle import adjoint, metrics
-    prob = w.c1()
-    _, g_exact = adjoint.grad_time_reversal(prob, "fp64", 1)
-    res = {}
-    for dtype, k in dtype_pairs:
-        gobj = pk.Gradient(prob, dtype, k)
-        gobj.forward(torch.from_numpy(prob.eps).cuda())
-        g = gobj.backward().cpu().numpy()
-        res["%s_k%d" % (dtype, k)] = {"rel_l2": metrics.rel_l2(g, g_exact),
-                                      "cosine": metrics.cosine_similarity(g, g_exact)}
-    return res
+def cosine(a, b) -> float:
+    """Eq. 2: cosine similarity of two gradients."""
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_gradient(name: str, seed: int):
+    """The FP64 oracle's exact gradient of this problem, stored by tests/golden/make_oracle_grads.py
+    (None if that file was not made)."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_grad_%s_seed%d.npy" % (name, seed))
+    return np.load(path) if os.path.exists(path) else None
 
 
 SWEEP_TYPES = ["fp32", "fp16", "bf16", "fp8_e4m3_scaled", "fp8_e4m3b11fnuz", "fp8_e5m2fnuz", "fp8_e4m3fnuz",
@@ -124,35 +126,52 @@ SWEEP_K = [1, 2, 4, 8, 16, 32]
 
 
 def run_sweep(args, w, pk, torch, dev):
-    """Mean cosine similarity (Eq. 2) of compressed-storage gradients against FP32 storage at
-    every step, over seeded random designs, for each storage type and k; one JSON line each."""
-    from oracle import metrics   # metric only; every gradient comes from the HIP path
+    """Every storage type x k on seeded random designs: storage, gradient agreement (Eq. 2
+    cosine and relative L2) with the FP64 oracle's exact gradient (where stored) and with the
+    plain FP32 full-storage GPU gradient, and fwd+rev Mcell-steps/s; one JSON line each."""
     preset, kw, _, _ = WORKLOADS[args.workload]
     probs = [w.make(preset, seed=s, **kw) for s in range(args.sweep_seeds)]
+    exact = [oracle_gradient(p.name, s) for s, p in enumerate(probs)]
     refs = []
     for p in probs:
         g = pk.Gradient(p, "fp32", 1, device=dev)
         g.forward(torch.from_numpy(p.eps).to(dev))
         refs.append(g.backward().cpu().numpy().copy())
     full = pk.store_config(pk.Problem(probs[0]), "fp32", 1).payload_bytes
+    cell_steps = probs[0].cells * probs[0].steps
     for dtype in SWEEP_TYPES:
         for k in SWEEP_K:
-            cos, rel = [], []
-            t0 = time.perf_counter()
-            for p, ref in zip(probs, refs):
+            row = {"cos_oracle": [], "rel_oracle": [], "cos_fp32": [], "rel_fp32": []}
+            rate = None
+            for s, (p, ref) in enumerate(zip(probs, refs)):
                 g = pk.Gradient(p, dtype, k, device=dev)
-                g.forward(torch.from_numpy(p.eps).to(dev))
-                gr = g.backward().cpu().numpy()
-                finite = bool(np.all(np.isfinite(gr)))
-                cos.append(metrics.cosine_similarity(gr, ref) if finite else float("nan"))
-                rel.append(metrics.rel_l2(gr, ref) if finite else float("nan"))
+                e = torch.from_numpy(p.eps).to(dev)
+                reps = 2 if s == 0 else 1          # seed 0 runs twice: the second call is timed
+                for r in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    g.forward(e)
+                    gr = g.backward().cpu().numpy()
+                    if r == 1:
+                        rate = cell_steps / (time.perf_counter() - t0) / 1e6
+                ok = bool(np.all(np.isfinite(gr)))
+                row["cos_fp32"].append(cosine(gr, ref) if ok else float("nan"))
+                row["rel_fp32"].append(rel_l2(gr, ref) if ok else float("nan"))
+                if exact[s] is not None:
+                    row["cos_oracle"].append(cosine(gr, exact[s]) if ok else float("nan"))
+                    row["rel_oracle"].append(rel_l2(gr, exact[s]) if ok else float("nan"))
             info = pk.store_config(pk.Problem(probs[0]), dtype, k)
-            print(json.dumps({"sweep": probs[0].name, "store_dtype": dtype, "k": k,
-                              "compression": round(full / info.payload_bytes, 3),
-                              "storage_GB": info.payload_bytes / 1e9,
-                              "cosine_mean": float(np.mean(cos)), "cosine_min": float(np.min(cos)),
-                              "rel_l2_mean": float(np.mean(rel)), "seeds": len(probs),
-                              "s_per_gradient": round((time.perf_counter() - t0) / len(probs), 4)}), flush=True)
+            line = {"sweep": probs[0].name, "store_dtype": dtype, "k": k,
+                    "compression": round(full / info.payload_bytes, 3), "storage_GB": info.payload_bytes / 1e9,
+                    "cos_vs_fp32_mean": float(np.mean(row["cos_fp32"])),
+                    "rel_l2_vs_fp32_mean": float(np.mean(row["rel_fp32"])),
+                    "Mcell_steps_per_s": round(rate, 1), "seeds": len(probs)}
+            if row["cos_oracle"]:
+                line.update({"cos_vs_oracle_mean": float(np.mean(row["cos_oracle"])),
+                             "cos_vs_oracle_min": float(np.min(row["cos_oracle"])),
+                             "rel_l2_vs_oracle_mean": float(np.mean(row["rel_oracle"])),
+                             "oracle_seeds": len(row["cos_oracle"])})
+            print(json.dumps(line), flush=True)
 
 
 def main():
@@ -301,9 +320,13 @@ def main():
                                          "same grid truncated to %d time steps: %.1f s on %s"
                                          % (args.cpu_sample_steps, dt_cpu, platform.processor() or
                                             platform.machine())}
-        out["grad_rel_err_vs_fp64_oracle"] = {
-            "workload": "c1_32cube (32^3, 8-cell CPML, 200 steps; the oracle-sized case)",
-            **oracle_grad_error([(dtype, k), ("fp8_e4m3_scaled", 16)])}
+    exact = oracle_gradient(prob.name, 0)
+    if exact is not None:
+        errs = {"%s_k%d" % (dtype, k): gobj.buf.grad.cpu().numpy()}
+        if not args.no_compressed:
+            errs["fp8_e4m3_scaled_k16"] = c_obj.buf.grad.cpu().numpy()
+        out["grad_err_vs_fp64_oracle"] = {
+            name: {"rel_l2": rel_l2(g, exact), "cosine": cosine(g, exact)} for name, g in errs.items()}
     print(json.dumps(out))
 
 
