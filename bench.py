@@ -255,10 +255,16 @@ def main():
         pk.timing_enable(False)
         return kt, t1 - t0
 
+    def progress(msg):
+        print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+    progress("%s: %d cells x %d steps, %s k=%d" % (prob.name, cells, T, dtype, k))
     elapsed, gobj = timed_run(dtype, k, args.steps, args.warmup)
+    progress("timed region: %.3f s for %d gradients" % (elapsed, args.steps))
     ms_per_step = elapsed / args.steps * 1e3
     value = cells * T * args.steps / elapsed / 1e6
     ktimes, kt_elapsed = kernel_times(gobj, args.steps)
+    progress("per-kernel event pass: %.3f s" % kt_elapsed)
 
     design_cells = int(np.prod(prob.design_shape))
     ab = algorithmic_bytes(prob, design_cells)
@@ -307,6 +313,7 @@ def main():
 
     if not args.no_compressed:
         c_el, c_obj = timed_run("fp8_e4m3_scaled", 16, args.steps, args.warmup)
+        progress("compressed timed region: %.3f s" % c_el)
         out["compressed"] = {"store_dtype": "fp8_e4m3_scaled", "k": 16,
                              "value": round(cells * T * args.steps / c_el / 1e6, 1),
                              "ms_per_step": round(c_el / args.steps * 1e3, 3),
@@ -314,6 +321,7 @@ def main():
                              "storage_reduction": gobj.info.payload_bytes / c_obj.info.payload_bytes}
 
     if not args.no_cpu_baseline:
+        progress("oracle baseline on the host, %d steps" % args.cpu_sample_steps)
         mcs, dt_cpu, sprob = oracle_baseline(prob_fn, args.cpu_sample_steps)
         out["cpu_baseline"] = {"value": round(mcs, 4), "unit": "Mcell-steps/s", "cores": 1, "kind": "oracle",
                                "sample": "FP64 NumPy oracle, time-reversal gradient (forward + reverse) of the "

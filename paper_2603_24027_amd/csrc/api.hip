@@ -164,7 +164,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     g.dbz0 = p->det_lo[2];      g.dnbz = p->det_hi[2] - p->det_lo[2];
     Tiling& t = pl->fwd;
     t.ty = env_int("FDTD_TILE_Y", 4) == 8 ? 8 : 4;
-    t.cz = env_int("FDTD_TILE_Z", 4) == 8 ? 8 : 4;
+    t.cz = env_int("FDTD_TILE_Z", 8) == 4 ? 4 : 8;
     t.ntx = (p->nx + TX - 1) / TX;
     t.nty = (p->ny + t.ty - 1) / t.ty;
     t.ntz = (p->nz + t.cz - 1) / t.cz;
@@ -180,7 +180,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     Tiling& r = pl->rev;
     r = t;
     r.ty = env_int("FDTD_REV_TILE_Y", t.ty) == 8 ? 8 : 4;
-    r.cz = env_int("FDTD_REV_TILE_Z", t.cz) == 8 ? 8 : 4;
+    r.cz = env_int("FDTD_REV_TILE_Z", 4) == 8 ? 8 : 4;
     pl->rev_x0 = pl->box_o[0] & ~31;
     r.ntx = (pl->box_o[0] + pl->box_n[0] - pl->rev_x0 + TX - 1) / TX;
     r.nty = (pl->box_n[1] + r.ty - 1) / r.ty;

@@ -667,9 +667,9 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_inject_shell(Grid g, float* __restrict__ F, const void* __restrict__ store,
                                                       Interp qE, Interp qH, int do_e, int do_h) {
     const int P = g.P;
-    const long long ax = (long long)g.my * g.mz, ay = (long long)g.mx * g.mz, az = (long long)g.mx * g.my;
-    const long long face = ax + ay + az;
-    long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const int ax = g.my * g.mz, ay = g.mx * g.mz, az = g.mx * g.my;   // face sizes (< 2^31: 24 N < 2^31)
+    const int face = ax + ay + az;
+    int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
     const bool high = t >= face;
     if (high) t -= face;
     if (t >= face || (high ? !do_e : !do_h)) return;
@@ -677,15 +677,13 @@ __global__ __launch_bounds__(256) void k_inject_shell(Grid g, float* __restrict_
     float* A = F + (high ? 0 : 3 * (long long)N);           // E for the high faces, H for the low ones
     const Interp& q = high ? qE : qH;
     const int b0 = high ? 6 : 0;
-    int x, y, z, c0, c1, blk;
-    long long u;
+    int x, y, z, c0, c1, blk, u;
     if (t < ax) {
-        u = t; blk = b0; y = P + (int)(u % g.my); z = P + (int)(u / g.my); x = high ? g.nx - P : P - 1; c0 = 1; c1 = 2;
+        u = t; blk = b0; y = P + u % g.my; z = P + u / g.my; x = high ? g.nx - P : P - 1; c0 = 1; c1 = 2;
     } else if (t < ax + ay) {
-        u = t - ax; blk = b0 + 2; x = P + (int)(u % g.mx); z = P + (int)(u / g.mx); y = high ? g.ny - P : P - 1;
-        c0 = 2; c1 = 0;
+        u = t - ax; blk = b0 + 2; x = P + u % g.mx; z = P + u / g.mx; y = high ? g.ny - P : P - 1; c0 = 2; c1 = 0;
     } else {
-        u = t - ax - ay; blk = b0 + 4; x = P + (int)(u % g.mx); y = P + (int)(u / g.mx); z = high ? g.nz - P : P - 1;
+        u = t - ax - ay; blk = b0 + 4; x = P + u % g.mx; y = P + u / g.mx; z = high ? g.nz - P : P - 1;
         c0 = 0; c1 = 1;
     }
     const int idx = x + g.nx * (y + g.ny * z);
