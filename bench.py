@@ -174,6 +174,34 @@ def run_sweep(args, w, pk, torch, dev):
             print(json.dumps(line), flush=True)
 
 
+DESIGN_CONFIGS = [("fp32", 1), ("fp8_e4m3_scaled", 4), ("fp8_e4m3_scaled", 8), ("fp8_e4m3_scaled", 16),
+                  ("fp8_e4m3_scaled", 32)]
+
+
+def run_design_loop(args, w, pk, torch, dev):
+    """Objective trajectories of the inverse-design loop with full and compressed interface
+    storage from the same seeded starts; one JSON line per (storage, seed)."""
+    from paper_2603_24027_amd.optimize import DesignLoop
+    preset, kw, _, _ = WORKLOADS[args.workload]
+    for seed in range(args.sweep_seeds):
+        prob = w.make(preset, seed=seed, **kw)
+        ref = None
+        for dtype, k in DESIGN_CONFIGS:
+            t0 = time.perf_counter()
+            loop = DesignLoop(prob, dtype, k, sigma=3.0, beta=8.0, lr=0.1, warmup=10, seed=seed, device=dev,
+                              eps_range=(float(prob.eps.min()), 12.25))
+            hist = loop.run(args.design_loop)
+            if ref is None:
+                ref = hist
+            print(json.dumps({"design_loop": prob.name, "store_dtype": dtype, "k": k, "seed": seed,
+                              "iterations": len(hist), "objective_first": hist[0], "objective_last": hist[-1],
+                              "gain": hist[-1] / hist[0],
+                              "max_rel_dev_from_fp32": float(np.max(np.abs(np.array(hist) - np.array(ref)) /
+                                                                    np.abs(np.array(ref)))),
+                              "history": [float("%.6e" % v) for v in hist],
+                              "s": round(time.perf_counter() - t0, 2)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +216,9 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="storage type x k sweep of gradient agreement (Fig. 3 analogue) instead of the benchmark")
     ap.add_argument("--sweep-seeds", type=int, default=3)
+    ap.add_argument("--design-loop", type=int, default=0, metavar="ITERS",
+                    help="run the inverse-design loop for ITERS iterations with FP32 k=1 and FP8 k in "
+                         "{4, 8, 16, 32} storage instead of the benchmark (Fig. 4 analogue)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -215,6 +246,9 @@ def main():
     if args.sweep:
         run_sweep(args, w, pk, torch, dev)
         return
+    if args.design_loop:
+        run_design_loop(args, w, pk, torch, dev)
+        return
 
     preset, kw, dtype, k = WORKLOADS[args.workload]
     prob_fn = lambda **extra: w.make(preset, **{**kw, **extra})
@@ -223,18 +257,28 @@ def main():
     T = prob.steps
     cells = prob.cells
 
+    fwd_rev_ms = {}
+
     def timed_run(dtype_, k_, steps, warmup):
         gobj = pk.Gradient(prob, dtype_, k_, device=dev)
         for _ in range(warmup):
             gobj.forward(eps)
             gobj.backward()
+        stream = torch.cuda.current_stream(dev)
+        marks = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+                  torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for a, b, c in marks:           # events on the stream the library launches on
+            a.record(stream)
             gobj.forward(eps)
+            b.record(stream)
             gobj.backward()
+            c.record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        fwd_rev_ms[(dtype_, k_)] = (float(np.mean([a.elapsed_time(b) for a, b, _ in marks])),
+                                    float(np.mean([b.elapsed_time(c) for _, b, c in marks])))
         return (t1 - t0), gobj
 
     def kernel_times(gobj, steps):
@@ -290,6 +334,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
+        "t_fwd_ms": round(fwd_rev_ms[(dtype, k)][0], 3),
+        "t_rev_ms": round(fwd_rev_ms[(dtype, k)][1], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -317,6 +363,8 @@ def main():
         out["compressed"] = {"store_dtype": "fp8_e4m3_scaled", "k": 16,
                              "value": round(cells * T * args.steps / c_el / 1e6, 1),
                              "ms_per_step": round(c_el / args.steps * 1e3, 3),
+                             "t_fwd_ms": round(fwd_rev_ms[("fp8_e4m3_scaled", 16)][0], 3),
+                             "t_rev_ms": round(fwd_rev_ms[("fp8_e4m3_scaled", 16)][1], 3),
                              "boundary_store_GB": c_obj.info.payload_bytes / 1e9,
                              "storage_reduction": gobj.info.payload_bytes / c_obj.info.payload_bytes}
 
