@@ -94,3 +94,36 @@ def test_paper_regime_fp8_k16_keeps_gradient_direction():
     cos = metrics.cosine_similarity(out["grad"], ref["grad"])
     say("  cosine %.6f rel-L2 %.3e" % (cos, metrics.rel_l2(out["grad"], ref["grad"])))
     assert cos >= 0.99
+
+
+def _oracle_gradient(name, seed):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "oracle_grad_%s_seed%d.npy" % (name, seed))
+    if not os.path.exists(path):
+        pytest.skip("stored oracle gradient %s not present (tests/golden/make_oracle_grads.py)" % path)
+    return np.load(path)
+
+
+def test_c2_fp32_gradient_matches_fp64_oracle():
+    # parity at the benchmark size against the oracle's exact gradient (stored by the oracle script)
+    require_gpu()
+    prob = w.c2(seed=0)
+    exact = _oracle_gradient(prob.name, 0)
+    g = gpu_run(prob, "fp32", 1, keep_fields=False)["grad"]
+    r, c = metrics.rel_l2(g, exact), metrics.cosine_similarity(g, exact)
+    say("c2 fp32 k=1 vs FP64 oracle: rel-L2 %.3e cosine %.12f" % (r, c))
+    assert r <= 1e-5 and c >= 1 - 1e-9
+
+
+@pytest.mark.parametrize("dtype,k,cos_min", [("fp8_e4m3_scaled", 8, 0.999), ("fp8_e4m3_scaled", 16, 0.998),
+                                             ("bf16", 4, 0.9999), ("fp8_e5m2fnuz", 4, 0.999)])
+def test_c3p_compressed_gradient_vs_fp64_oracle(dtype, k, cos_min):
+    # the paper's sampling (about 136 steps per period): compressed storage against the exact gradient
+    require_gpu()
+    prob = w.c3p(seed=0)
+    exact = _oracle_gradient(prob.name, 0)
+    g = gpu_run(prob, dtype, k, keep_fields=False)["grad"]
+    c = metrics.cosine_similarity(g, exact)
+    say("c3p %s k=%d vs FP64 oracle: cosine %.6f rel-L2 %.3e" % (dtype, k, c, metrics.rel_l2(g, exact)))
+    assert c >= cos_min
