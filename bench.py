@@ -37,8 +37,9 @@ WORKLOADS = {
     "c5": ("c5", {}, "fp32", 1),
     "c3p": ("c3p", {}, "fp32", 1),
 }
-KERNEL_SOURCES = ["paper_2603_24027_amd/csrc/common.h", "paper_2603_24027_amd/csrc/forward.hip",
-                  "paper_2603_24027_amd/csrc/reverse.hip", "paper_2603_24027_amd/csrc/api.hip"]
+KERNEL_SOURCES = ["paper_2603_24027_amd/csrc/common.h", "paper_2603_24027_amd/csrc/march.h",
+                  "paper_2603_24027_amd/csrc/forward.hip", "paper_2603_24027_amd/csrc/reverse.hip",
+                  "paper_2603_24027_amd/csrc/api.hip"]
 
 
 def kernel_source_hash() -> str:

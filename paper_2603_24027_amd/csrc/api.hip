@@ -163,7 +163,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     g.dby0 = p->det_lo[1] / BY; g.dnby = (p->det_hi[1] - 1) / BY - g.dby0 + 1;
     g.dbz0 = p->det_lo[2];      g.dnbz = p->det_hi[2] - p->det_lo[2];
     Tiling& t = pl->fwd;
-    t.ty = env_int("FDTD_TILE_Y", 8) == 4 ? 4 : 8;
+    t.ty = env_int("FDTD_TILE_Y", 4) == 8 ? 8 : 4;
     t.cz = env_int("FDTD_TILE_Z", 8) == 4 ? 4 : 8;
     t.ntx = (p->nx + TX - 1) / TX;
     t.nty = (p->ny + t.ty - 1) / t.ty;
