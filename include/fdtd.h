@@ -82,7 +82,8 @@ extern "C" {
  * Problem statement: grid with PML faces, permittivity map, source, detector
  * and Courant number (Section 2 and Eq. 1; PML from Section 1).
  *
- *   nx, ny, nz      full grid in cells, PML included (each >= 1; 24 * cells < 2^31,
+ *   nx, ny, nz      full grid in cells, PML included (each >= 1; 24 * S < 2^31 for the
+ *                   component stride S of fdtd_store_info_t.fields_bytes,
  *                   and the two copies of the PML auxiliaries below 2 GiB)
  *   pml             PML thickness P on all six faces (0 <= P <= FDTD_MAX_PML,
  *                   2P < each extent); the interior I is [P, n-P) on each axis
@@ -136,7 +137,8 @@ typedef struct {
     uint64_t payload_bytes;     /* slices * values_per_slice * storage bytes (Fig. 3)    */
     uint64_t scale_bytes;       /* 12 float scales per kept step (FP8 only)              */
     uint64_t store_bytes;       /* size of the store buffer (payload, padding, scales)   */
-    uint64_t fields_bytes;      /* 6 * cells * 4: Ex Ey Ez Hx Hy Hz                      */
+    uint64_t fields_bytes;      /* 6 * S * 4: Ex Ey Ez Hx Hy Hz, component c of cell i at
+                                   float c * S + i; S = fields_bytes / 24 >= cells         */
     uint64_t psi_bytes;         /* forward PML auxiliaries (H side in two copies)        */
     uint64_t adj_psi_bytes;     /* backward PML auxiliaries (two copies, ping-pong)      */
     uint64_t workspace_bytes;   /* coefficient tables, source profile, loss partials,

@@ -34,6 +34,13 @@ int fail(int code, const char* fmt, ...) {
 uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
 // Tuning override for tile sizes (read once per call; defaults otherwise).
+#ifndef FDTD_FIELD_PAD
+#define FDTD_FIELD_PAD 1056
+#endif
+// Floats between consecutive field components (cells rounded up to a 128-byte line,
+// plus FDTD_FIELD_PAD floats).
+int64_t field_stride(int64_t cells) { return ((cells + 31) / 32) * 32 + FDTD_FIELD_PAD; }
+
 int env_int(const char* name, int dflt) {
     const char* v = std::getenv(name);
     return v && *v ? std::atoi(v) : dflt;
@@ -99,8 +106,8 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(FDTD_EINVAL, "grid extents must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
     // kernels address the six field components as one buffer with 32-bit byte offsets below 2^31
-    if (p->ny > 4 * 65535 || p->nz > 65535 || 24 * (int64_t)p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
-        return fail(FDTD_EINVAL, "grid too large: 24 * cells must stay below 2^31");
+    if (p->ny > 4 * 65535 || p->nz > 65535 || 24 * field_stride((int64_t)p->nx * p->ny * p->nz) >= ((int64_t)1 << 31))
+        return fail(FDTD_EINVAL, "grid too large: 24 * field stride must stay below 2^31");
     if (p->steps < 1) return fail(FDTD_EINVAL, "steps must be >= 1 (got %d)", p->steps);
     if (p->pml < 0 || p->pml > FDTD_MAX_PML) return fail(FDTD_EINVAL, "pml must be in [0, %d]", FDTD_MAX_PML);
     const int n[3] = {p->nx, p->ny, p->nz};
@@ -134,7 +141,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     g.nx = p->nx; g.ny = p->ny; g.nz = p->nz; g.P = P;
     g.periodic = p->boundary;
     g.mx = p->nx - 2 * P; g.my = p->ny - 2 * P; g.mz = p->nz - 2 * P;
-    g.N = N;
+    g.N = field_stride(N);
     g.dt = (float)dt;
     g.slab[0] = 2LL * P * p->ny * p->nz;
     g.slab[1] = 2LL * P * p->nx * p->nz;
@@ -198,7 +205,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     in.payload_bytes = slices * (uint64_t)vps * vbytes;
     in.scale_bytes = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? slices * 12 * 4 : 0;
     in.store_bytes = std::max<uint64_t>(256, (uint64_t)g.scale_off + align_up(in.scale_bytes, 256));
-    in.fields_bytes = 6ull * (uint64_t)N * 4;
+    in.fields_bytes = 6ull * (uint64_t)g.N * 4;
     in.psi_bytes = std::max<uint64_t>(256, 2 * pl->psi_floats * 4);
     in.adj_psi_bytes = std::max<uint64_t>(512, 2 * pl->psi_floats * 4);
     pl->ws_coef = 0;

@@ -38,7 +38,7 @@ struct Grid {
     int nx, ny, nz, P;
     int periodic;
     int mx, my, mz;          // interior extents n - 2P
-    long long N;             // cells
+    long long N;             // floats between field components (>= cells)
     float dt;
     long long psi_off[3];    // start of each axis' four slab arrays in a PML buffer (floats)
     long long slab[3];       // slab size per axis (floats)

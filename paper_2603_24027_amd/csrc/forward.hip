@@ -258,7 +258,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     b.psi = make_rsrc(psi, 2 * psib);
     b.hin = hcopy ? psib : 0u;
     b.hout = hcopy ? 0u : psib;
-    b.eps = make_rsrc(eps, (uint32_t)N * 4u);
+    b.eps = make_rsrc(eps, (uint32_t)(c.plane * g.nz) * 4u);
     // a kept step records into its slice of the store (a store can exceed 4 GiB; one
     // slice cannot), the scaled FP8 type into the FP32 staging buffer
     if constexpr (REC == 3) b.rec = make_rsrc(staging, (uint32_t)g.vps * 4u);

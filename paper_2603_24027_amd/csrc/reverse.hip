@@ -263,7 +263,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
     const uint32_t psib = (uint32_t)g.psi_total * 4u;
     b.A0 = make_rsrc(A0, (uint32_t)(6 * c.N) * 4u);
     b.A1 = make_rsrc(A1, (uint32_t)(6 * c.N) * 4u);
-    b.eps = make_rsrc(eps, (uint32_t)c.N * 4u);
+    b.eps = make_rsrc(eps, (uint32_t)(c.plane * g.nz) * 4u);
     b.psi = make_rsrc(psi, 2 * psib);
     b.pin = pcopy ? psib : 0u;
     b.pout = pcopy ? 0u : psib;
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     RevBufs b;
     b.F0 = make_rsrc(F0, (uint32_t)(6 * N) * 4u);
     b.F1 = make_rsrc(F1, (uint32_t)(6 * N) * 4u);
-    b.eps = make_rsrc(eps, (uint32_t)N * 4u);
+    b.eps = make_rsrc(eps, (uint32_t)(c.plane * g.nz) * 4u);
     b.src = make_rsrc(g.src_profile, (uint32_t)((g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1]) *
                                                 (g.src_hi[2] - g.src_lo[2])) * 4u);
     c.own = make_col(g, c.x, c.y);

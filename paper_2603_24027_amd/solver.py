@@ -115,16 +115,16 @@ class Gradient:
         self.info = store_config(self.problem, dtype, k)
         i = self.info
         dev = self.device
-        n = int(i.cells)
+        self.stride = int(i.fields_bytes) // 24          # floats between field components
         self.buf = Buffers(
-            fields=torch.empty(6 * n, dtype=torch.float32, device=dev),
+            fields=torch.empty(6 * self.stride, dtype=torch.float32, device=dev),
             psi=_bytes(i.psi_bytes, dev),
             store=_bytes(i.store_bytes, dev),
             workspace=_bytes(i.workspace_bytes, dev),
             loss=torch.zeros((), dtype=torch.float64, device=dev),
             series=torch.zeros(self.problem.desc.steps, dtype=torch.float64, device=dev) if series else None)
         if with_backward:
-            self.buf.adj_fields = torch.empty(6 * n, dtype=torch.float32, device=dev)
+            self.buf.adj_fields = torch.empty(6 * self.stride, dtype=torch.float32, device=dev)
             self.buf.adj_psi = _bytes(i.adj_psi_bytes, dev)
             self.buf.grad = torch.empty(self.problem.design_shape, dtype=torch.float64, device=dev)
         self.record = FdtdRecord()
@@ -160,7 +160,8 @@ class Gradient:
 
     def fields(self):
         """(E, H) views of the field buffer, each [3, nz, ny, nx]."""
-        f = self.buf.fields.view(6, *self.problem.shape)
+        n = int(self.info.cells)
+        f = self.buf.fields.view(6, self.stride)[:, :n].unflatten(1, self.problem.shape)
         return f[:3], f[3:]
 
 
