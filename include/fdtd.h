@@ -99,8 +99,12 @@ extern "C" {
  *   src_wave        host, T floats: J^n sampled at t = (n + 1/2) dt
  *   src_profile     host, box-volume floats in [z][y][x] order: J on the box
  *                   at step n is src_wave[n] * src_profile[...]
- *   det_lo, det_hi  detector box (inside I): loss L = sum_{n<T} sum_{p in D} |E^{n+1}(p)|^2
+ *   det_lo, det_hi  detector box D (inside I)
  *   des_lo, des_hi  design box (inside I): dL/deps is returned for these cells
+ *   loss            0: L = sum_{n<T} sum_{p in D} |E^{n+1}(p)|^2;
+ *                   1, 2, 3: L = sum_{n<T} sum_{p in D} (E^{n+1}(p) x H^{n+1/2}(p))_{x, y, z},
+ *                   the Poynting flux along x, y or z (Section 3's transmission
+ *                   metric), E and H taken at the same cell index
  */
 typedef struct {
     int32_t nx, ny, nz;
@@ -118,6 +122,7 @@ typedef struct {
     const float* src_profile;
     int32_t det_lo[3], det_hi[3];
     int32_t des_lo[3], des_hi[3];
+    int32_t loss;
 } fdtd_problem_t;
 
 /* Recorder configuration: storage type (FDTD_STORE_*) and subsampling k >= 1.

@@ -76,27 +76,35 @@ def _grad_term(solver: Solver, Ebar: np.ndarray, UJ_design: np.ndarray) -> np.nd
 
 
 def loss_and_history(solver: Solver):
-    """Forward run keeping E^{n+1}[D] and (U^n - J^n)[design] for every step."""
+    """Forward run keeping E^{n+1}[D], H^{n+1/2}[D] and (U^n - J^n)[design] for every step."""
     T = solver.p.steps
     s = State(solver.shape)
-    E_det, UJ_des = [], []
+    E_det, H_det, UJ_des = [], [], []
     loss = 0.0
     for n in range(T):
         UJ = solver.step(s, n)
         E_det.append(s.E[(slice(None),) + solver.det_sl].copy())
+        H_det.append(s.H[(slice(None),) + solver.det_sl].copy())
         UJ_des.append(UJ[(slice(None),) + solver.des_sl].copy())
-        loss += solver.detector_energy(s)
-    return loss, E_det, UJ_des, s
+        loss += solver.detector_loss(s)
+    return loss, E_det, H_det, UJ_des, s
+
+
+def seed(solver: Solver, a: AdjointState, E_det: np.ndarray, H_det: np.ndarray):
+    """Add this step's loss derivatives to the adjoint state (before the step's transpose)."""
+    gE, gH = solver.loss_seeds(E_det, H_det)
+    a.E[(slice(None),) + solver.det_sl] += gE
+    a.H[(slice(None),) + solver.det_sl] += gH
 
 
 def grad_full_storage(problem, match_fp32: bool = False):
     """(loss, dL/deps on the design box) by the stored-history adjoint."""
     solver = Solver(problem, match_fp32)
-    loss, E_det, UJ_des, _ = loss_and_history(solver)
+    loss, E_det, H_det, UJ_des, _ = loss_and_history(solver)
     a = AdjointState(solver.shape)
     g = np.zeros(problem.design_shape)
     for n in range(problem.steps - 1, -1, -1):
-        a.E[(slice(None),) + solver.det_sl] += 2.0 * E_det[n]
+        seed(solver, a, E_det[n], H_det[n])
         g += _grad_term(solver, a.E, UJ_des[n])
         adjoint_e_half(solver, a)
         adjoint_h_half(solver, a)
@@ -121,7 +129,7 @@ def record_forward(solver: Solver, mode: str = "fp64", k: int = 1, steps: int = 
         if n in keep:
             kept_H[n] = [codec.roundtrip_block(b, mode) for b in solver.shell_H(s)]  # H^{n+1/2}
         solver.e_update(s, n)
-        losses[n] = solver.detector_energy(s)
+        losses[n] = solver.detector_loss(s)
     return float(np.sum(losses)), losses, s, kept_H, kept_E
 
 
@@ -151,7 +159,7 @@ def grad_time_reversal(problem, mode: str = "fp64", k: int = 1, match_fp32: bool
     trace = {}
     I = (slice(None),) + solver.int_sl
     for n in range(T - 1, -1, -1):
-        a.E[(slice(None),) + solver.det_sl] += 2.0 * s.E[(slice(None),) + solver.det_sl]
+        seed(solver, a, s.E[(slice(None),) + solver.det_sl], s.H[(slice(None),) + solver.det_sl])
         if have_shell:
             solver.put_shell_H(s, shell_at(n, T, k, kept_H))          # H^{n+1/2} on the low shell
         UJ = solver.e_inverse(s, n)                                     # E^n on I
@@ -174,7 +182,7 @@ def loss_only(problem, match_fp32: bool = False) -> float:
     loss = 0.0
     for n in range(problem.steps):
         solver.step(s, n)
-        loss += solver.detector_energy(s)
+        loss += solver.detector_loss(s)
     return loss
 
 

@@ -229,6 +229,32 @@ class Solver:
         """sum over the detector box of |E|^2 (all three components, same cell index)."""
         return float(np.sum(s.E[(slice(None),) + self.det_sl] ** 2))
 
+    def detector_flux(self, s: State, axis: int) -> float:
+        """sum over the detector box of the Poynting vector component along `axis`,
+        (E x H)_axis, from E^{n+1} and H^{n+1/2} at the same cell index."""
+        E = s.E[(slice(None),) + self.det_sl]
+        H = s.H[(slice(None),) + self.det_sl]
+        a, b = (axis + 1) % 3, (axis + 2) % 3
+        return float(np.sum(E[a] * H[b] - E[b] * H[a]))
+
+    def detector_loss(self, s: State) -> float:
+        """This step's loss term: |E|^2 (loss 0) or the flux along x, y, z (loss 1, 2, 3)."""
+        kind = getattr(self.p, "loss", 0)
+        return self.detector_energy(s) if kind == 0 else self.detector_flux(s, kind - 1)
+
+    def loss_seeds(self, E_det: np.ndarray, H_det: np.ndarray):
+        """(dL/dE^{n+1}, dL/dH^{n+1/2}) of one step's loss term on the detector box."""
+        kind = getattr(self.p, "loss", 0)
+        if kind == 0:
+            return 2.0 * E_det, np.zeros_like(H_det)
+        axis = kind - 1
+        a, b = (axis + 1) % 3, (axis + 2) % 3
+        gE = np.zeros_like(E_det)
+        gH = np.zeros_like(H_det)
+        gE[a], gE[b] = H_det[b], -H_det[a]       # d/dE_a (E_a H_b - E_b H_a) = H_b, d/dE_b = -H_a
+        gH[b], gH[a] = E_det[a], -E_det[b]
+        return gE, gH
+
     # -- interface shell (Section 2: interface slices between volume and PML) -------------
     def shell_H(self, s: State):
         """S_H = H^{n+1/2} at index P-1 on the three low faces (tangential components).
@@ -310,7 +336,7 @@ def run_forward(solver: Solver, steps: int = None, snapshots=()):
         snaps[0] = s.copy()
     for n in range(T):
         solver.step(s, n)
-        losses[n] = solver.detector_energy(s)
+        losses[n] = solver.detector_loss(s)
         if (n + 1) in snapshots:
             snaps[n + 1] = s.copy()
     return s, losses, snaps

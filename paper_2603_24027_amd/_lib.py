@@ -48,6 +48,7 @@ class FdtdProblem(ctypes.Structure):
         ("src_profile", ctypes.POINTER(ctypes.c_float)),
         ("det_lo", I3), ("det_hi", I3),
         ("des_lo", I3), ("des_hi", I3),
+        ("loss", ctypes.c_int32),
     ]
 
 

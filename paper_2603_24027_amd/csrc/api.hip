@@ -122,6 +122,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
         !std::isfinite(p->pml_alpha_max))
         return fail(FDTD_EINVAL, "invalid PML grading parameters");
     if (p->src_comp < 0 || p->src_comp > 2) return fail(FDTD_EINVAL, "src_comp must be 0, 1 or 2");
+    if (p->loss < 0 || p->loss > 3) return fail(FDTD_EINVAL, "loss must be 0 (|E|^2) or 1, 2, 3 (flux along x, y, z)");
     if (!p->src_wave || !p->src_profile) return fail(FDTD_EINVAL, "source signal and profile must not be NULL");
     if (!box_inside_interior(p->src_lo, p->src_hi, n, p->pml))
         return fail(FDTD_EREGION, "source box must be non-empty and inside the interior");
@@ -153,6 +154,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     if (8 * (int64_t)g.psi_total >= ((int64_t)1 << 31))
         return fail(FDTD_EINVAL, "PML too large: the two copies of the auxiliaries must stay below 2 GiB");
     g.src_comp = p->src_comp;
+    g.loss = p->loss;
     for (int d = 0; d < 3; ++d) {
         g.src_lo[d] = p->src_lo[d]; g.src_hi[d] = p->src_hi[d];
         g.det_lo[d] = p->det_lo[d]; g.det_hi[d] = p->det_hi[d];
@@ -225,7 +227,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     const int32_t ints[] = {p->nx, p->ny, p->nz, p->pml, p->steps, p->boundary, p->pml_order, p->src_comp,
                             p->src_lo[0], p->src_lo[1], p->src_lo[2], p->src_hi[0], p->src_hi[1], p->src_hi[2],
                             p->det_lo[0], p->det_lo[1], p->det_lo[2], p->det_hi[0], p->det_hi[1], p->det_hi[2],
-                            p->des_lo[0], p->des_lo[1], p->des_lo[2], p->des_hi[0], p->des_hi[1], p->des_hi[2]};
+                            p->des_lo[0], p->des_lo[1], p->des_lo[2], p->des_hi[0], p->des_hi[1], p->des_hi[2], p->loss};
     const double dbl[] = {p->courant, p->pml_sigma_scale, p->pml_kappa_max, p->pml_alpha_max};
     h = fnv1a(h, ints, sizeof ints);
     h = fnv1a(h, dbl, sizeof dbl);

@@ -45,6 +45,7 @@ struct Grid {
     long long psi_total;     // floats in one PML buffer
     const float* coef;       // device coefficient table (6 * 2P floats)
     // source
+    int loss;                // 0: |E|^2 on the detector; 1, 2, 3: Poynting flux along x, y, z
     int src_comp;
     int src_lo[3], src_hi[3];
     const float* src_profile;
@@ -389,6 +390,26 @@ __device__ inline float nb_plus(const float* f, long long idx, int i, int n, lon
 __device__ inline float nb_minus(const float* f, long long idx, int i, int n, long long stride, int periodic) {
     if (i > 0) return f[idx - stride];
     return periodic ? f[idx + (long long)(n - 1) * stride] : 0.0f;
+}
+
+// One step's loss term at one detector cell from E^{n+1} and H^{n+1/2} at that index:
+// |E|^2 (loss 0) or (E x H) along x, y, z (loss 1, 2, 3).
+__device__ inline double loss_term(int loss, const float e[3], const float h[3]) {
+    if (loss == 0) return (double)e[0] * e[0] + (double)e[1] * e[1] + (double)e[2] * e[2];
+    const int a = loss % 3, b = (loss + 1) % 3;      // axis loss-1: components axis+1, axis+2
+    return (double)e[a] * h[b] - (double)e[b] * h[a];
+}
+
+// Its derivatives (dL/dE^{n+1}, dL/dH^{n+1/2}) at that cell.
+__device__ inline void loss_seeds(int loss, const float e[3], const float h[3], float gE[3], float gH[3]) {
+    gE[0] = gE[1] = gE[2] = gH[0] = gH[1] = gH[2] = 0.0f;
+    if (loss == 0) {
+        gE[0] = 2.0f * e[0]; gE[1] = 2.0f * e[1]; gE[2] = 2.0f * e[2];
+        return;
+    }
+    const int a = loss % 3, b = (loss + 1) % 3;
+    gE[a] = h[b]; gE[b] = -h[a];
+    gH[b] = e[a]; gH[a] = -e[b];
 }
 
 // dt / eps of the E update; the forward step, its reversal and its adjoint all use

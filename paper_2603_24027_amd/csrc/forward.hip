@@ -207,8 +207,7 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
     e[1] = eo[1] + cc * u[1];
     e[2] = eo[2] + cc * u[2];
     bst3v(b.F1, L.o, sk, nb, e);
-    if (c.live && in_box(x, y, k, g.det_lo, g.det_hi))
-        e2 += (double)e[0] * e[0] + (double)e[1] * e[1] + (double)e[2] * e[2];
+    if (c.live && in_box(x, y, k, g.det_lo, g.det_hi)) e2 += loss_term(g.loss, e, h);
     hx_prev = h[0];
     hy_prev = h[1];
     eo[0] = in.e1[0]; eo[1] = in.e1[1]; eo[2] = in.e1[2];

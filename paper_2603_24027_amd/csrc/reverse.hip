@@ -462,22 +462,32 @@ __device__ __forceinline__ void e_rev(const Grid& g, const float (*hc)[TY + 2][E
 }
 
 // The owner of an interior cell on the design or detector box: this step's loss
-// seed 2 E^{n+1} is added to Ebar in place (the adjoint sweep reads it seeded),
-// and the gradient epsbar -= (dt/eps^2) Ebar . (U - J) accumulates in FP64.
+// derivatives (2 E^{n+1} for |E|^2; H- and E-terms for a flux) are added to Ebar and
+// Hbar in place (the adjoint sweep reads them seeded), and the gradient
+// epsbar -= (dt/eps^2) Ebar . (U - J) accumulates in FP64.  Eb0 is the adjoint field
+// buffer (Ebar, then Hbar at component stride g.N).
 __device__ __forceinline__ void grad_and_seed(const Grid& g, float* __restrict__ Eb0, double* __restrict__ grad,
-                                              int x, int y, int z, int idx, const float e1[3], float ep,
-                                              const float u[3]) {
+                                              int x, int y, int z, int idx, const float e1[3], const float h[3],
+                                              float ep, const float u[3]) {
     const bool det = in_box(x, y, z, g.det_lo, g.det_hi), des = in_box(x, y, z, g.des_lo, g.des_hi);
     if (!det && !des) return;
-    const int N = (int)g.N;
+    const long long N = g.N;
     float eb[3] = {Eb0[idx], Eb0[N + idx], Eb0[2 * N + idx]};
     if (det) {
-        eb[0] += 2.0f * e1[0];
-        eb[1] += 2.0f * e1[1];
-        eb[2] += 2.0f * e1[2];
+        float gE[3], gH[3];
+        loss_seeds(g.loss, e1, h, gE, gH);
+        eb[0] += gE[0];
+        eb[1] += gE[1];
+        eb[2] += gE[2];
         Eb0[idx] = eb[0];
         Eb0[N + idx] = eb[1];
         Eb0[2 * N + idx] = eb[2];
+        if (g.loss != 0) {
+            float* Hb0 = Eb0 + 3 * N;
+            Hb0[idx] += gH[0];
+            Hb0[N + idx] += gH[1];
+            Hb0[2 * N + idx] += gH[2];
+        }
     }
     if (des) {
         const int dx = g.des_hi[0] - g.des_lo[0], dy = g.des_hi[1] - g.des_lo[1];
@@ -508,7 +518,10 @@ __device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const R
     const bool zst = owned && z >= 0 && z_interior(g, z);
     const uint32_t nb = (uint32_t)c.N << 2;
     bst3v(b.F1, zst ? L.st : OOB, uni(zst ? (uint32_t)(z * c.plane) << 2 : 0u), nb, e);
-    if (owned && c.live && interior) grad_and_seed(g, Eb0, grad, c.own.x, c.own.y, z, c.own.xy + z * c.plane, e1, ep, u);
+    if (owned && c.live && interior) {
+        const float h[3] = {hc[0][row + 1][lane + 1], hc[1][row + 1][lane + 1], hc[2][row + 1][lane + 1]};
+        grad_and_seed(g, Eb0, grad, c.own.x, c.own.y, z, c.own.xy + z * c.plane, e1, h, ep, u);
+    }
     if (c.pex >= 0) {
         e_rev<TY>(g, hc, hp, c.pex + 1, c.pey + 1, c.xcol, z, xe1, xep, xsp, xsh, wave, e, u, interior);
         sE[0][c.pey][c.pex] = e[0];

@@ -57,7 +57,8 @@ class Problem:
             pml_kappa_max=desc.pml_kappa_max, pml_alpha_max=desc.pml_alpha_max, src_comp=desc.src_comp,
             src_lo=_i3(desc.src_lo), src_hi=_i3(desc.src_hi),
             src_wave=self._wave.ctypes.data_as(fp), src_profile=self._profile.ctypes.data_as(fp),
-            det_lo=_i3(desc.det_lo), det_hi=_i3(desc.det_hi), des_lo=_i3(desc.des_lo), des_hi=_i3(desc.des_hi))
+            det_lo=_i3(desc.det_lo), det_hi=_i3(desc.det_hi), des_lo=_i3(desc.des_lo), des_hi=_i3(desc.des_hi),
+            loss=int(getattr(desc, "loss", 0)))
 
     @property
     def shape(self):

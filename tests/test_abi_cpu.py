@@ -39,6 +39,9 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(_lib.FdtdRecord) == 24
     assert _lib.FdtdProblem.courant.offset == 24
     assert _lib.FdtdProblem.src_wave.offset % 8 == 0
+    # the loss kind follows the design box; the struct is padded to its 8-byte alignment
+    assert _lib.FdtdProblem.loss.offset == _lib.FdtdProblem.des_hi.offset + 12
+    assert ctypes.sizeof(_lib.FdtdProblem) == (_lib.FdtdProblem.loss.offset + 4 + 7) // 8 * 8
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5", "tiny", "ragged"])
@@ -90,6 +93,8 @@ def test_validation_errors_before_any_device_work():
     assert _call_forward(replace(base, pml=6)) == _lib.FDTD_EINVAL       # 2P >= n
     assert _call_forward(replace(base, boundary=1)) == _lib.FDTD_EINVAL  # periodic with a PML
     assert _call_forward(replace(base, steps=0)) == _lib.FDTD_EINVAL
+    assert _call_forward(replace(base, loss=4)) == _lib.FDTD_EINVAL       # unknown loss kind
+    assert _call_forward(replace(base, loss=-1)) == _lib.FDTD_EINVAL
     assert _call_forward(base, k=0) == _lib.FDTD_ESTORE
     assert _call_forward(base, dtype="fp8_e4m3_scaled", k=4) == _lib.FDTD_EINVAL
 

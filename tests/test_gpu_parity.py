@@ -249,3 +249,49 @@ def test_graph_replay_matches_eager():
             assert loss == ref["loss"], (dtype, rep)
             assert np.array_equal(series, ref["series"]), (dtype, rep)
             assert np.array_equal(grad, ref["grad"]), (dtype, rep)
+
+
+# --------------------------------------------------------------------------- Poynting-flux objective
+
+FLUX_CASES = {
+    "tiny_flux_z": lambda: replace(w.tiny(), loss=3),
+    "c1_flux_z": lambda: replace(w.c1(), loss=3),
+    "ragged_flux_x": lambda: replace(w.ragged(), loss=1, pml_kappa_max=3.0),
+    "periodic_flux_y": lambda: replace(_periodic_problem(), loss=2),
+}
+
+
+@pytest.mark.parametrize("case", list(FLUX_CASES))
+def test_flux_objective_forward_and_gradient(case):
+    require_gpu()
+    prob = FLUX_CASES[case]()
+    say("flux objective", case, "loss kind", prob.loss)
+    out = gpu_run(prob, series=True)
+    _, losses, _ = yee.run_forward(yee.Solver(prob, match_fp32=True))
+    scale = np.sum(np.abs(losses))          # the flux changes sign: compare against the size of its terms
+    assert abs(out["loss"] - losses.sum()) <= 1e-5 * scale
+    assert np.max(np.abs(out["series"] - losses)) <= 1e-4 * np.max(np.abs(losses))
+    L, g = adjoint.grad_time_reversal(prob, "fp64", 1, match_fp32=True)
+    r = rel(out["grad"], g)
+    cos = metrics.cosine_similarity(out["grad"], g)
+    say("  rel-L2 %.3e cosine %.12f" % (r, cos))
+    assert r <= 1e-4 and cos >= 1 - 1e-8
+
+
+def test_flux_gradient_against_finite_differences():
+    require_gpu()
+    prob = replace(w.tiny(), loss=3)
+    out = gpu_run(prob)
+    fd = adjoint.grad_finite_difference(prob, np.arange(out["grad"].size), h=1e-4)
+    g = out["grad"].ravel()
+    assert np.all(np.abs(g - fd) <= 1e-4 * np.max(np.abs(fd)) + 1e-4 * np.abs(fd))
+
+
+def test_flux_compressed_against_oracle_compressed():
+    require_gpu()
+    prob = replace(w.c1(), loss=3)
+    out = gpu_run(prob, "fp8_e4m3_scaled", 4)
+    _, g = adjoint.grad_time_reversal(prob, ORACLE_MODE["fp8_e4m3_scaled"], 4, match_fp32=True)
+    cos = metrics.cosine_similarity(out["grad"], g)
+    say("  fp8 k=4 flux: cosine vs oracle-compressed %.8f" % cos)
+    assert cos >= 0.9999

@@ -63,6 +63,7 @@ class Problem:
     des_hi: Box = (0, 0, 0)
     eps: np.ndarray = field(default_factory=lambda: np.zeros((0, 0, 0), np.float32))
     wavelength: float = 0.0      # informational (cells)
+    loss: int = 0                # 0: sum of |E|^2 on the detector; 1, 2, 3: Poynting flux along x, y, z
 
     @property
     def shape(self) -> Tuple[int, int, int]:
