@@ -105,6 +105,11 @@ extern "C" {
  *                   1, 2, 3: L = sum_{n<T} sum_{p in D} (E^{n+1}(p) x H^{n+1/2}(p))_{x, y, z},
  *                   the Poynting flux along x, y or z (Section 3's transmission
  *                   metric), E and H taken at the same cell index
+ *   msrc_comp       0, 1, 2 = Mx, My, Mz: an optional magnetic current, dH/dt = -curl E - M
+ *                   (with J, the two sheets of a total-field/scattered-field plane wave)
+ *   msrc_lo, msrc_hi  its box (inside I); an empty box means none
+ *   msrc_wave       host, T floats: M^n (enters the H update of step n); NULL if none
+ *   msrc_profile    host, box-volume floats in [z][y][x] order; NULL if none
  */
 typedef struct {
     int32_t nx, ny, nz;
@@ -123,6 +128,10 @@ typedef struct {
     int32_t det_lo[3], det_hi[3];
     int32_t des_lo[3], des_hi[3];
     int32_t loss;
+    int32_t msrc_comp;
+    int32_t msrc_lo[3], msrc_hi[3];
+    const float* msrc_wave;
+    const float* msrc_profile;
 } fdtd_problem_t;
 
 /* Recorder configuration: storage type (FDTD_STORE_*) and subsampling k >= 1.

@@ -125,7 +125,7 @@ def record_forward(solver: Solver, mode: str = "fp64", k: int = 1, steps: int = 
     for n in range(T):
         if n in keep:
             kept_E[n] = [codec.roundtrip_block(b, mode) for b in solver.shell_E(s)]  # E^n
-        solver.h_update(s)
+        solver.h_update(s, n)
         if n in keep:
             kept_H[n] = [codec.roundtrip_block(b, mode) for b in solver.shell_H(s)]  # H^{n+1/2}
         solver.e_update(s, n)
@@ -167,7 +167,7 @@ def grad_time_reversal(problem, mode: str = "fp64", k: int = 1, match_fp32: bool
         adjoint_e_half(solver, a)
         if have_shell:
             solver.put_shell_E(s, shell_at(n, T, k, kept_E))          # E^n on the high shell
-        solver.h_inverse(s)                                             # H^{n-1/2} on I
+        solver.h_inverse(s, n)                                          # H^{n-1/2} on I
         adjoint_h_half(solver, a)
         if return_trace:
             trace[n] = (s.E[I].copy(), s.H[I].copy())

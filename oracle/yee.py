@@ -182,6 +182,12 @@ class Solver:
                        slice(p.src_lo[0], p.src_hi[0]))
         self.src_profile = np.asarray(p.src_profile, np.float32).astype(np.float64)
         self.src_wave = np.asarray(p.src_wave, np.float32).astype(np.float64)
+        # optional magnetic current sheet (the H half of a total-field/scattered-field source)
+        self.msrc_comp = getattr(p, "msrc_comp", 0)
+        mlo, mhi = getattr(p, "msrc_lo", (0, 0, 0)), getattr(p, "msrc_hi", (0, 0, 0))
+        self.msrc_sl = (slice(mlo[2], mhi[2]), slice(mlo[1], mhi[1]), slice(mlo[0], mhi[0]))
+        self.msrc_profile = np.asarray(getattr(p, "msrc_profile", np.zeros((0, 0, 0))), np.float32).astype(np.float64)
+        self.msrc_wave = np.asarray(getattr(p, "msrc_wave", np.zeros(0)), np.float32).astype(np.float64)
         self.det_sl = (slice(p.det_lo[2], p.det_hi[2]), slice(p.det_lo[1], p.det_hi[1]),
                        slice(p.det_lo[0], p.det_hi[0]))
         self.des_sl = p.design_slices()
@@ -196,14 +202,25 @@ class Solver:
             J[self.src_comp][self.src_sl] = self.src_wave[n] * self.src_profile
         return J
 
+    def magnetic_current(self, n: int):
+        """M^n on the full grid (enters the H update as dH/dt = -curl E - M), or None."""
+        if self.msrc_wave.size == 0 or n is None or n >= self.msrc_wave.size:
+            return None
+        M = np.zeros((3,) + self.shape)
+        M[self.msrc_comp][self.msrc_sl] = self.msrc_wave[n] * self.msrc_profile
+        return M
+
     # -- forward ------------------------------------------------------------
-    def h_update(self, s: State):
-        """H^{n-1/2} -> H^{n+1/2} from E^n, with the H-side PML recursions."""
+    def h_update(self, s: State, n: int = None):
+        """H^{n-1/2} -> H^{n+1/2} from E^n, with the H-side PML recursions and M^n."""
         for t, (c, d, sg, f) in enumerate(H_TERMS):
             b, a, kinv = self.coef_H[d]
             g = dplus(s.E[f], d, self.periodic)
             s.psi_H[t] = b * s.psi_H[t] + a * g
             s.H[c] -= self.dt * sg * (kinv * g + s.psi_H[t])
+        M = self.magnetic_current(n)
+        if M is not None:
+            s.H -= self.dt * M
 
     def curl_h(self, s: State) -> np.ndarray:
         """U = curl H with the E-side PML recursions applied (updates psi_E)."""
@@ -222,7 +239,7 @@ class Solver:
         return UJ
 
     def step(self, s: State, n: int) -> np.ndarray:
-        self.h_update(s)
+        self.h_update(s, n)
         return self.e_update(s, n)
 
     def detector_energy(self, s: State) -> float:
@@ -317,11 +334,14 @@ class Solver:
         s.E[I] -= (self.dt / self.eps[self.int_sl]) * UJ[I]
         return UJ
 
-    def h_inverse(self, s: State):
-        """H^{n+1/2} -> H^{n-1/2} on I from E^n (interior + high shell)."""
+    def h_inverse(self, s: State, n: int = None):
+        """H^{n+1/2} -> H^{n-1/2} on I from E^n (interior + high shell) and M^n."""
         dH = np.zeros((3,) + self.shape)
         for (c, d, sg, f) in H_TERMS:
             dH[c] += self.dt * sg * dplus(s.E[f], d, self.periodic)
+        M = self.magnetic_current(n)
+        if M is not None:
+            dH += self.dt * M
         I = (slice(None),) + self.int_sl
         s.H[I] += dH[I]
 

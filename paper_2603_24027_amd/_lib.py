@@ -49,6 +49,10 @@ class FdtdProblem(ctypes.Structure):
         ("det_lo", I3), ("det_hi", I3),
         ("des_lo", I3), ("des_hi", I3),
         ("loss", ctypes.c_int32),
+        ("msrc_comp", ctypes.c_int32),
+        ("msrc_lo", I3), ("msrc_hi", I3),
+        ("msrc_wave", ctypes.POINTER(ctypes.c_float)),
+        ("msrc_profile", ctypes.POINTER(ctypes.c_float)),
     ]
 
 

@@ -63,6 +63,8 @@ struct Plan {
     uint64_t psi_floats = 0;
     int per_step = 0;
     int64_t src_volume = 0;
+    int64_t msrc_volume = 0;       // 0: no magnetic current
+    uint64_t ws_mprofile = 0;
     std::vector<float> coef;   // 12 P floats
     uint64_t hash = 0;
 };
@@ -126,6 +128,14 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     if (!p->src_wave || !p->src_profile) return fail(FDTD_EINVAL, "source signal and profile must not be NULL");
     if (!box_inside_interior(p->src_lo, p->src_hi, n, p->pml))
         return fail(FDTD_EREGION, "source box must be non-empty and inside the interior");
+    const bool has_m = p->msrc_hi[0] > p->msrc_lo[0] && p->msrc_hi[1] > p->msrc_lo[1] && p->msrc_hi[2] > p->msrc_lo[2];
+    if (has_m) {
+        if (p->msrc_comp < 0 || p->msrc_comp > 2) return fail(FDTD_EINVAL, "msrc_comp must be 0, 1 or 2");
+        if (!p->msrc_wave || !p->msrc_profile)
+            return fail(FDTD_EINVAL, "magnetic current signal and profile must not be NULL");
+        if (!box_inside_interior(p->msrc_lo, p->msrc_hi, n, p->pml))
+            return fail(FDTD_EREGION, "magnetic current box must be inside the interior");
+    }
     if (!box_inside_interior(p->det_lo, p->det_hi, n, p->pml))
         return fail(FDTD_EREGION, "detector box must be non-empty and inside the interior");
     if (!box_inside_interior(p->des_lo, p->des_hi, n, p->pml))
@@ -155,6 +165,11 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
         return fail(FDTD_EINVAL, "PML too large: the two copies of the auxiliaries must stay below 2 GiB");
     g.src_comp = p->src_comp;
     g.loss = p->loss;
+    g.msrc_comp = has_m ? p->msrc_comp : 0;
+    for (int d = 0; d < 3; ++d) {
+        g.msrc_lo[d] = has_m ? p->msrc_lo[d] : 0;
+        g.msrc_hi[d] = has_m ? p->msrc_hi[d] : 0;
+    }
     for (int d = 0; d < 3; ++d) {
         g.src_lo[d] = p->src_lo[d]; g.src_hi[d] = p->src_hi[d];
         g.det_lo[d] = p->det_lo[d]; g.det_hi[d] = p->det_hi[d];
@@ -212,7 +227,10 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     in.adj_psi_bytes = std::max<uint64_t>(512, 2 * pl->psi_floats * 4);
     pl->ws_coef = 0;
     pl->ws_profile = align_up(12ull * P * 4, 256);
-    pl->ws_partials = pl->ws_profile + align_up((uint64_t)pl->src_volume * 4, 256);
+    pl->msrc_volume = has_m ? (int64_t)(p->msrc_hi[0] - p->msrc_lo[0]) * (p->msrc_hi[1] - p->msrc_lo[1]) *
+                                  (p->msrc_hi[2] - p->msrc_lo[2]) : 0;
+    pl->ws_mprofile = pl->ws_profile + align_up((uint64_t)pl->src_volume * 4, 256);
+    pl->ws_partials = pl->ws_mprofile + align_up((uint64_t)pl->msrc_volume * 4, 256);
     pl->ws_staging = pl->ws_partials + align_up((uint64_t)p->steps * pl->per_step * 8, 256);
     const uint64_t staging = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? align_up((uint64_t)vps * 4, 256) : 0;
     pl->ws_fields = pl->ws_staging + staging;
@@ -233,6 +251,13 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     h = fnv1a(h, dbl, sizeof dbl);
     h = fnv1a(h, p->src_wave, (size_t)p->steps * 4);
     h = fnv1a(h, p->src_profile, (size_t)pl->src_volume * 4);
+    if (pl->msrc_volume > 0) {
+        const int32_t mi[] = {p->msrc_comp, p->msrc_lo[0], p->msrc_lo[1], p->msrc_lo[2],
+                              p->msrc_hi[0], p->msrc_hi[1], p->msrc_hi[2]};
+        h = fnv1a(h, mi, sizeof mi);
+        h = fnv1a(h, p->msrc_wave, (size_t)p->steps * 4);
+        h = fnv1a(h, p->msrc_profile, (size_t)pl->msrc_volume * 4);
+    }
     pl->hash = h;
     return FDTD_OK;
 }
@@ -389,6 +414,7 @@ int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const 
     Grid g = pl.g;
     g.coef = (const float*)(ws + pl.ws_coef);
     g.src_profile = (const float*)(ws + pl.ws_profile);
+    g.msrc_profile = (const float*)(ws + pl.ws_mprofile);
     double* partials = (double*)(ws + pl.ws_partials);
     float* staging = (float*)(ws + pl.ws_staging);
 
@@ -398,6 +424,8 @@ int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const 
     host.assign(pl.ws_partials, 0);
     std::memcpy(host.data() + pl.ws_coef, pl.coef.data(), pl.coef.size() * 4);
     std::memcpy(host.data() + pl.ws_profile, prob->src_profile, (size_t)pl.src_volume * 4);
+    if (pl.msrc_volume > 0)
+        std::memcpy(host.data() + pl.ws_mprofile, prob->msrc_profile, (size_t)pl.msrc_volume * 4);
     if (hipMemcpyAsync(ws, host.data(), pl.ws_partials, hipMemcpyHostToDevice, s) != hipSuccess)
         return fail(FDTD_EHIP, "fdtd_forward: upload of coefficient tables failed");
 
@@ -409,6 +437,7 @@ int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const 
     const int start = T & 1;
     const bool fp8 = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED && g.vps > 0;
     const float* wave = prob->src_wave;
+    auto mwave = [&](int n) { return pl.msrc_volume > 0 ? prob->msrc_wave[n] : 0.0f; };
     auto enqueue = [&](hipStream_t q) {
         launch_fill(F[start], 6 * N, 0.0f, q);
         launch_fill(psi, 2 * (long long)pl.psi_floats, 0.0f, q);
@@ -416,7 +445,7 @@ int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const 
             const int slice = ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1;
             const float* in = F[(start + n) & 1];
             float* out = F[(start + n + 1) & 1];
-            launch_fwd_step(g, pl.fwd, in, out, psi, n & 1, eps, wave[n],
+            launch_fwd_step(g, pl.fwd, in, out, psi, n & 1, eps, wave[n], mwave(n),
                             partials + (int64_t)n * pl.per_step, store, staging, slice, q);
             if (slice >= 0 && fp8) launch_rec_quant(g, staging, store, slice, q);
         }
@@ -451,12 +480,14 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
     Grid g = pl.g;
     g.coef = (const float*)(ws + pl.ws_coef);
     g.src_profile = (const float*)(ws + pl.ws_profile);
+    g.msrc_profile = (const float*)(ws + pl.ws_mprofile);
 
     const int T = prob->steps, k = cfg->k;
     const int64_t N = g.N;
     float* Fp[2] = {fields, (float*)(ws + pl.ws_fields)};                       // primal
     float* Fa[2] = {adj_fields, (float*)(ws + pl.ws_fields + pl.info.fields_bytes)};   // adjoint
     const float* wave = prob->src_wave;
+    auto mwave = [&](int n) { return pl.msrc_volume > 0 ? prob->msrc_wave[n] : 0.0f; };
     auto enqueue = [&](hipStream_t q) {
         launch_fill(Fa[0], 6 * N, 0.0f, q);
         launch_fill(adj_psi, 2 * (long long)pl.psi_floats, 0.0f, q);
@@ -473,7 +504,7 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
             // the interior reversal, which reads the E part of that shell
             launch_inject_shell(g, pn, store, interp_for(n, T, k), n >= 1 ? interp_for(n - 1, T, k) : none, 1, n >= 1,
                                 q);
-            launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], grad_eps, q);
+            launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], mwave(n), grad_eps, q);
             launch_adj_step(g, pl.fwd, ao, an, eps, adj_psi, st & 1, q);
         }
         if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, q);

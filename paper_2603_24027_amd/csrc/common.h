@@ -46,6 +46,9 @@ struct Grid {
     const float* coef;       // device coefficient table (6 * 2P floats)
     // source
     int loss;                // 0: |E|^2 on the detector; 1, 2, 3: Poynting flux along x, y, z
+    int msrc_comp;           // magnetic current sheet (empty box: none)
+    int msrc_lo[3], msrc_hi[3];
+    const float* msrc_profile;
     int src_comp;
     int src_lo[3], src_hi[3];
     const float* src_profile;
@@ -449,7 +452,7 @@ void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 struct Tiling;
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                     const float* eps, float wave, double* partials,
+                     const float* eps, float wave, float mwave, double* partials,
                      void* store, float* staging, int slice, hipStream_t s);
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s);
 void launch_loss_final(const double* partials, int steps, int per_step, double* loss, double* series,
@@ -457,8 +460,8 @@ void launch_loss_final(const double* partials, int steps, int per_step, double* 
 void launch_inject_shell(const Grid& g, float* F, const void* store, Interp qE, Interp qH, int do_e, int do_h,
                          hipStream_t s);
 void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
-                     const float* F0, float* F1, const float* eps, float* Eb0, float wave, double* grad,
-                     hipStream_t s);
+                     const float* F0, float* F1, const float* eps, float* Eb0, float wave, float mwave,
+                     double* grad, hipStream_t s);
 void launch_adj_step(const Grid& g, const Tiling& t, const float* A0, float* A1, const float* eps, float* psi,
                      int pcopy, hipStream_t s);
 void launch_scale_grad(double* grad, long long n, const double* scale, hipStream_t s);

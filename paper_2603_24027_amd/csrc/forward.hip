@@ -53,7 +53,7 @@ __device__ inline void h_terms(const float (*cur)[TY + 2][EXT], const float (*nx
 
 // Buffer resources of one forward sweep.
 struct FwdBufs {
-    rsrc_t F0, F1, psi, eps, src;                    // fields in / out (E then H), both PML copies
+    rsrc_t F0, F1, psi, eps, src, msrc;              // fields in / out (E then H), both PML copies
     rsrc_t rec;                                      // kept step: its store slice, or the FP32 staging
     uint32_t hin, hout;                              // byte offsets of the H-side PML copies in / out
 };
@@ -63,7 +63,7 @@ struct FwdBufs {
 // values serve as neighbours) and of the ring position; the own cell (live lanes);
 // the halo cell; the source box column; PML auxiliaries of the own and halo cells.
 struct FwdLanes {
-    uint32_t eo, er, o, hc, src;
+    uint32_t eo, er, o, hc, src, m, mh;       // ... and the magnetic-current sheet (own, halo)
     PsiLane po, ph;
     bool ysl;                 // the own row lies in a y slab (uniform across a wave)
 };
@@ -73,7 +73,7 @@ struct FwdLanes {
 // (own cell and the halo cell), eps, the source profile (0 outside the source box)
 // and the PML auxiliaries of plane k.
 struct PlaneIn {
-    float e1[3], er[3], h0[3], hh0[3], ep, sp;
+    float e1[3], er[3], h0[3], hh0[3], ep, sp, mp, mph;   // mp, mph: magnetic-current profile (own, halo)
     float ph[6], pe[6], phh[6];
 };
 
@@ -100,6 +100,10 @@ __device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, c
     uint32_t ss;
     const uint32_t vs = src_plane(g, k, L.src, ss);
     d.sp = bldv(b.src, vs, ss);
+    uint32_t ms;
+    const bool mz = box_plane(g.msrc_lo, g.msrc_hi, k, ms);
+    d.mp = bldv(b.msrc, mz ? L.m : OOB, ms);
+    d.mph = bldv(b.msrc, mz ? L.mh : OOB, ms);
     const PsiPlane pH = psi_plane(g, 0, k, b.hin), pE = psi_plane(g, 1, k, 0);
     bld_psi_v(b.psi, L.po, pH, d.ph);
     bld_psi_v(b.psi, L.po, pE, d.pe);
@@ -115,7 +119,7 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
                                           float (*sE)[3][TY + 2][EXT], float (*sH)[TY + 1][TX + 1],
                                           const CoefTile<TY, CZ>& ct, int lz, int cur, int k,
                                           const PlaneIn& in, float eo[3], float& hx_prev, float& hy_prev, double& e2,
-                                          float wave) {
+                                          float wave, float mwave) {
     const int nxt = 1 - cur;
     const int P = c.P, x = c.x, y = c.y, row = c.row, lane = c.lane;
     const uint32_t nb = (uint32_t)c.N << 2;
@@ -141,9 +145,10 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
         if (L.ysl) cpml_y(cf_y(ct, 1, row + 1), t, ph);
         if (pH.zs) cpml_z(cf_z(ct, 1, lz), t, ph);
         const float dt = g.dt;
-        h[0] = c.live ? in.h0[0] - dt * (t[0] - t[1]) : 0.0f;
-        h[1] = c.live ? in.h0[1] - dt * (t[2] - t[3]) : 0.0f;
-        h[2] = c.live ? in.h0[2] - dt * (t[4] - t[5]) : 0.0f;
+        const float m = dt * mwave * in.mp;     // magnetic current (0 outside its sheet)
+        h[0] = c.live ? in.h0[0] - dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f) : 0.0f;
+        h[1] = c.live ? in.h0[1] - dt * (t[2] - t[3]) - (g.msrc_comp == 1 ? m : 0.0f) : 0.0f;
+        h[2] = c.live ? in.h0[2] - dt * (t[4] - t[5]) - (g.msrc_comp == 2 ? m : 0.0f) : 0.0f;
     }
     bst3v(b.F1, L.o, sk + 3 * nb, nb, h);
     bst_psi_v(b.psi, L.po, pH, ph);
@@ -175,9 +180,10 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
             h_terms<TY>(sE[cur], sE[nxt], c.hex, c.hey, t);
             cpml_apply(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, lz), t, phh);
             const float dt = g.dt;
-            hh[0] = in.hh0[0] - dt * (t[0] - t[1]);
-            hh[1] = in.hh0[1] - dt * (t[2] - t[3]);
-            hh[2] = in.hh0[2] - dt * (t[4] - t[5]);
+            const float m = dt * mwave * in.mph;
+            hh[0] = in.hh0[0] - dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f);
+            hh[1] = in.hh0[1] - dt * (t[2] - t[3]) - (g.msrc_comp == 1 ? m : 0.0f);
+            hh[2] = in.hh0[2] - dt * (t[4] - t[5]) - (g.msrc_comp == 2 ? m : 0.0f);
         }
         sH[0][c.hey][c.hex] = hh[0];
         sH[1][c.hey][c.hex] = hh[1];
@@ -226,8 +232,8 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
 template <int TY, int REC, int CZ>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FWD_WAVES))) void k_fwd_step(
     Grid g, Tiling tl, const float* __restrict__ F0, float* __restrict__ F1, float* __restrict__ psi, int hcopy,
-    const float* __restrict__ eps, float wave, double* __restrict__ partials, void* __restrict__ store,
-    float* __restrict__ staging, int slice) {
+    const float* __restrict__ eps, float wave, float mwave, double* __restrict__ partials,
+    void* __restrict__ store, float* __restrict__ staging, int slice) {
     __shared__ float sE[2][3][TY + 2][EXT];
     __shared__ float sH[3][TY + 1][TX + 1];
     __shared__ CoefTile<TY, CZ> ct;
@@ -264,6 +270,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     else if constexpr (REC >= 0) b.rec = make_rsrc((char*)store + (long long)slice * g.slice_stride, (uint32_t)g.slice_stride);
     const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
     b.src = make_rsrc(g.src_profile, (uint32_t)(sxn * syn * (g.src_hi[2] - g.src_lo[2])) * 4u);
+    b.msrc = make_rsrc(g.msrc_profile, (uint32_t)((g.msrc_hi[0] - g.msrc_lo[0]) * (g.msrc_hi[1] - g.msrc_lo[1]) *
+                                                  (g.msrc_hi[2] - g.msrc_lo[2])) * 4u);
 
     // columns this thread touches: its own, one position of the LDS ring, one halo H cell
     c.own = make_col(g, c.x, c.y);
@@ -289,6 +297,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     Ln.hc = lane_off(c.hc.xy >= 0, c.hc.xy);
     Ln.src = lane_off(c.live && c.x >= g.src_lo[0] && c.x < g.src_hi[0] && c.y >= g.src_lo[1] && c.y < g.src_hi[1],
                       (c.x - g.src_lo[0]) + sxn * (c.y - g.src_lo[1]));
+    Ln.m = box_lane(g.msrc_lo, g.msrc_hi, c.own);
+    Ln.mh = box_lane(g.msrc_lo, g.msrc_hi, c.hc);
     Ln.po = psi_lane(g, c.own, c.live);
     Ln.ph = psi_lane(g, c.hc, c.hc.xy >= 0);
     Ln.ysl = c.own.sy >= 0;
@@ -314,6 +324,9 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
         PsiLane lm = Ln.po;
         if (zm < 0) lm.x = lm.y = lm.z = OOB;
         bld_psi_v(b.psi, lm, pm, p);
+        uint32_t msm;
+        const bool mzm = zm >= 0 && box_plane(g.msrc_lo, g.msrc_hi, zm, msm);
+        const float mpm = bldv(b.msrc, mzm ? Ln.m : OOB, msm);
         load_plane_in<TY>(g, b, Ln, c, k0, pin[0]);
         #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -328,8 +341,9 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
         float t[6];
         h_terms<TY>(sE[0], sE[1], lane + 1, row + 1, t);
         cpml_apply(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), t, p);
-        hx_prev = pro ? h0[0] - g.dt * (t[0] - t[1]) : 0.0f;
-        hy_prev = pro ? h0[1] - g.dt * (t[2] - t[3]) : 0.0f;
+        const float m = g.dt * mwave * mpm;
+        hx_prev = pro ? h0[0] - g.dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f) : 0.0f;
+        hy_prev = pro ? h0[1] - g.dt * (t[2] - t[3]) - (g.msrc_comp == 1 ? m : 0.0f) : 0.0f;
     }
     __syncthreads();   // the first plane overwrites sE[0], which the prologue has just read
     double e2 = 0.0;
@@ -341,7 +355,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
             load_plane_in<TY>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
         if (k < k1)
             fwd_plane<TY, REC, CZ>(g, b, Ln, c, sE, sH, ct, kk + 1, (kk + 1) & 1, k, pin[kk & 1], eo, hx_prev,
-                                   hy_prev, e2, wave);
+                                   hy_prev, e2, wave, mwave);
     }
     // detector partial of this tile (tiles intersecting the detector only; uniform per block)
     const int dx = tix - tl.dtx0, dy = tiy - tl.dty0, dz = tiz - tl.dtz0;
@@ -404,31 +418,31 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
 
 template <int TY, int CZ>
 static void launch_fwd_step_t(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                              const float* eps, float wave, double* partials, void* store, float* staging, int slice,
-                              hipStream_t s) {
+                              const float* eps, float wave, float mwave, double* partials, void* store,
+                              float* staging, int slice, hipStream_t s) {
     const dim3 grid(t.count), block(TX, TY);
     if (slice < 0 || g.P == 0) {
         launch_kernel(K_FWD_STEP, k_fwd_step<TY, -1, CZ>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
-                      partials, store, staging, slice);
+                      mwave, partials, store, staging, slice);
         return;
     }
     with_dtype(g.dtype, [&]<int DT>() {
         launch_kernel(K_FWD_STEP, k_fwd_step<TY, DT, CZ>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
-                      partials, store, staging, slice);
+                      mwave, partials, store, staging, slice);
     });
 }
 
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                     const float* eps, float wave, double* partials, void* store, float* staging, int slice,
-                     hipStream_t s) {
+                     const float* eps, float wave, float mwave, double* partials, void* store, float* staging,
+                     int slice, hipStream_t s) {
     if (t.ty == 4 && t.cz == 4)
-        launch_fwd_step_t<4, 4>(g, t, F0, F1, psi, hcopy, eps, wave, partials, store, staging, slice, s);
+        launch_fwd_step_t<4, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
     else if (t.ty == 4)
-        launch_fwd_step_t<4, 8>(g, t, F0, F1, psi, hcopy, eps, wave, partials, store, staging, slice, s);
+        launch_fwd_step_t<4, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
     else if (t.cz == 4)
-        launch_fwd_step_t<8, 4>(g, t, F0, F1, psi, hcopy, eps, wave, partials, store, staging, slice, s);
+        launch_fwd_step_t<8, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
     else
-        launch_fwd_step_t<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, partials, store, staging, slice, s);
+        launch_fwd_step_t<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
 }
 
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s) {

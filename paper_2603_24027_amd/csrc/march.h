@@ -299,9 +299,23 @@ __device__ inline void bst3v(rsrc_t r, uint32_t v, uint32_t s, uint32_t nb, cons
     bstv(r, v, s + 2 * nb, o[2]);
 }
 __device__ inline uint32_t lane_off(bool on, int idx) { return on ? (uint32_t)idx << 2 : OOB; }
+
+// Offsets into a [z][y][x] profile over the box [lo, hi): the lane part for column c
+// (OOB outside the box in x-y) and the plane part for plane z (false outside in z).
+__device__ inline uint32_t box_lane(const int lo[3], const int hi[3], const Col& c) {
+    const bool in = c.xy >= 0 && c.x >= lo[0] && c.x < hi[0] && c.y >= lo[1] && c.y < hi[1];
+    return lane_off(in, (c.x - lo[0]) + (hi[0] - lo[0]) * (c.y - lo[1]));
+}
+__device__ inline bool box_plane(const int lo[3], const int hi[3], int z, uint32_t& s);
 // a value the caller knows to be wave-uniform, kept in a scalar register (the buffer
 // instructions take their uniform offset from one)
 __device__ inline uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+__device__ inline bool box_plane(const int lo[3], const int hi[3], int z, uint32_t& s) {
+    const bool in = z >= lo[2] && z < hi[2];
+    s = uni(in ? (uint32_t)((z - lo[2]) * (hi[0] - lo[0]) * (hi[1] - lo[1])) << 2 : 0u);
+    return in;
+}
 
 // Per-lane part of the byte offsets of a column's PML auxiliaries: x slab
 // sx + 2P y, y slab x + nx sy, z slab x + nx y (OOB outside the slab or when off).

@@ -368,7 +368,7 @@ struct Box {            // the region prim_rev sweeps: I plus a one-cell shell
 };
 
 struct RevBufs {
-    rsrc_t F0, F1, eps, src;   // primal fields in / out (E then H)
+    rsrc_t F0, F1, eps, src, msrc;   // primal fields in / out (E then H), source profiles
 };
 
 // What the primal reversal reads for plane k, loaded one plane ahead: H^{n+1/2}
@@ -377,6 +377,7 @@ struct RevBufs {
 struct RevIn {
     float h[3], rh[3], e[3], xe[3], ep, xep, sp, xsp;
     float sh[3], xsh[3];      // E^n of the high-face interface shell (0 elsewhere)
+    float mp;                 // magnetic-current profile of the own cell at plane k (0 off the sheet)
 };
 
 // Loop-invariant per-lane byte offsets: H of the own column and ring position
@@ -385,7 +386,7 @@ struct RevIn {
 // the high-face shell cells of both positions (shk: on the x or y face, for
 // interior planes; shz: interior in x and y, for the z face plane).
 struct RevLanes {
-    uint32_t h, r, e, xe, src, xsrc, st, shk, shz, xshk, xshz;
+    uint32_t h, r, e, xe, src, xsrc, st, shk, shz, xshk, xshz, m;
 };
 
 template <int TY>
@@ -429,6 +430,9 @@ __device__ __forceinline__ void load_rev_in(const Grid& g, const RevBufs& b, con
     const bool sz = z1 >= 0 && src_z(g, z1, ss);
     d.sp = bldv(b.src, sz ? L.src : OOB, ss);
     d.xsp = bldv(b.src, sz ? L.xsrc : OOB, ss);
+    uint32_t ms;
+    const bool mz = box_plane(g.msrc_lo, g.msrc_hi, k, ms);
+    d.mp = bldv(b.msrc, mz ? L.m : OOB, ms);
     // the shell values were written into the output buffer before this sweep
     const bool zh = z1 >= 0 && z1 == g.nz - g.P;
     bld3v(b.F1, zi ? L.shk : (zh ? L.shz : OOB), s1, nb, d.sh);
@@ -540,7 +544,7 @@ __device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const R
 template <int TY, int CZ>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_REV_WAVES))) void k_prim_rev(
     Grid g, Tiling tl, Box bx, const float* __restrict__ F0, float* __restrict__ F1, const float* __restrict__ eps,
-    float* __restrict__ Eb0, float wave, double* __restrict__ grad) {
+    float* __restrict__ Eb0, float wave, float mwave, double* __restrict__ grad) {
     __shared__ float sH[2][3][TY + 2][EXT];       // H^{n+1/2}, extended planes
     __shared__ float sE[2][3][TY + 1][TX + 1];     // E^n on the tile plus the +x column / +y row
     const int L = logical_tile(tl.count);
@@ -567,6 +571,8 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     b.eps = make_rsrc(eps, (uint32_t)(c.plane * g.nz) * 4u);
     b.src = make_rsrc(g.src_profile, (uint32_t)((g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1]) *
                                                 (g.src_hi[2] - g.src_lo[2])) * 4u);
+    b.msrc = make_rsrc(g.msrc_profile, (uint32_t)((g.msrc_hi[0] - g.msrc_lo[0]) * (g.msrc_hi[1] - g.msrc_lo[1]) *
+                                                  (g.msrc_hi[2] - g.msrc_lo[2])) * 4u);
     c.own = make_col(g, c.x, c.y);
     c.rlx = c.rly = -1;
     c.ring.xy = -1;
@@ -591,6 +597,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     Ln.src = src_lane(g, c.own);
     Ln.xsrc = src_lane(g, c.xcol);
     Ln.st = lane_off(c.live && xy_interior(g, c.own), c.own.xy);
+    Ln.m = box_lane(g.msrc_lo, g.msrc_hi, c.own);
     {
         auto shell = [&](const Col& q, uint32_t& k_off, uint32_t& z_off) {
             const bool iI = q.x >= P && q.x < g.nx - P, jI = q.y >= P && q.y < g.ny - P;
@@ -667,6 +674,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
             h[0] = sH[hc][0][row + 1][lane + 1] + dt * ((sE[ec][2][row + 1][lane] - ezc) - (sE[en][1][row][lane] - eyc));
             h[1] = sH[hc][1][row + 1][lane + 1] + dt * ((sE[en][0][row][lane] - exc) - (sE[ec][2][row][lane + 1] - ezc));
             h[2] = sH[hc][2][row + 1][lane + 1] + dt * ((sE[ec][1][row][lane + 1] - eyc) - (sE[ec][0][row + 1][lane] - exc));
+            const float m = dt * mwave * in.mp;     // the magnetic current of the step, 0 off its sheet
+            h[0] += g.msrc_comp == 0 ? m : 0.0f;
+            h[1] += g.msrc_comp == 1 ? m : 0.0f;
+            h[2] += g.msrc_comp == 2 ? m : 0.0f;
         }
         bst3v(b.F1, kI ? Ln.st : OOB, uni(((uint32_t)(k * c.plane) << 2) + 3 * nb), nb, h);
     }
@@ -725,21 +736,21 @@ void launch_adj_step(const Grid& g, const Tiling& t, const float* A0, float* A1,
 
 template <int TY, int CZ>
 static void launch_prim_rev_t(const Grid& g, const Tiling& t, const Box& b, const float* F0, float* F1,
-                              const float* eps, float* Eb0, float wave, double* grad, hipStream_t s) {
+                              const float* eps, float* Eb0, float wave, float mwave, double* grad, hipStream_t s) {
     launch_kernel(K_PRIM_REV, k_prim_rev<TY, CZ>, dim3(t.count), dim3(TX, TY), s, g, t, b, F0, F1, eps, Eb0, wave,
-                  grad);
+                  mwave, grad);
 }
 
 void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
-                     const float* F0, float* F1, const float* eps, float* Eb0, float wave, double* grad,
+                     const float* F0, float* F1, const float* eps, float* Eb0, float wave, float mwave, double* grad,
                      hipStream_t s) {
     Box b;
     for (int d = 0; d < 3; ++d) { b.o[d] = box_o[d]; b.n[d] = box_n[d]; }
     b.tx0 = tile_x0;
-    if (t.ty == 4 && t.cz == 4) launch_prim_rev_t<4, 4>(g, t, b, F0, F1, eps, Eb0, wave, grad, s);
-    else if (t.ty == 4) launch_prim_rev_t<4, 8>(g, t, b, F0, F1, eps, Eb0, wave, grad, s);
-    else if (t.cz == 4) launch_prim_rev_t<8, 4>(g, t, b, F0, F1, eps, Eb0, wave, grad, s);
-    else launch_prim_rev_t<8, 8>(g, t, b, F0, F1, eps, Eb0, wave, grad, s);
+    if (t.ty == 4 && t.cz == 4) launch_prim_rev_t<4, 4>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
+    else if (t.ty == 4) launch_prim_rev_t<4, 8>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
+    else if (t.cz == 4) launch_prim_rev_t<8, 4>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
+    else launch_prim_rev_t<8, 8>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
 }
 
 void launch_inject_shell(const Grid& g, float* F, const void* store, Interp qE, Interp qH, int do_e, int do_h,

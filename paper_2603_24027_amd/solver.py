@@ -50,6 +50,9 @@ class Problem:
         self.desc = desc
         self._wave = np.ascontiguousarray(desc.src_wave, np.float32)
         self._profile = np.ascontiguousarray(desc.src_profile, np.float32)
+        self._mwave = np.ascontiguousarray(getattr(desc, "msrc_wave", np.zeros(0)), np.float32)
+        self._mprofile = np.ascontiguousarray(getattr(desc, "msrc_profile", np.zeros(0)), np.float32)
+        has_m = self._mwave.size > 0 and self._mprofile.size > 0
         fp = ctypes.POINTER(ctypes.c_float)
         self.c = FdtdProblem(
             nx=desc.nx, ny=desc.ny, nz=desc.nz, pml=desc.pml, steps=desc.steps, boundary=desc.boundary,
@@ -58,7 +61,12 @@ class Problem:
             src_lo=_i3(desc.src_lo), src_hi=_i3(desc.src_hi),
             src_wave=self._wave.ctypes.data_as(fp), src_profile=self._profile.ctypes.data_as(fp),
             det_lo=_i3(desc.det_lo), det_hi=_i3(desc.det_hi), des_lo=_i3(desc.des_lo), des_hi=_i3(desc.des_hi),
-            loss=int(getattr(desc, "loss", 0)))
+            loss=int(getattr(desc, "loss", 0)),
+            msrc_comp=int(getattr(desc, "msrc_comp", 0)),
+            msrc_lo=_i3(getattr(desc, "msrc_lo", (0, 0, 0)) if has_m else (0, 0, 0)),
+            msrc_hi=_i3(getattr(desc, "msrc_hi", (0, 0, 0)) if has_m else (0, 0, 0)),
+            msrc_wave=self._mwave.ctypes.data_as(fp) if has_m else None,
+            msrc_profile=self._mprofile.ctypes.data_as(fp) if has_m else None)
 
     @property
     def shape(self):

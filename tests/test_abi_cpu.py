@@ -39,9 +39,13 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(_lib.FdtdRecord) == 24
     assert _lib.FdtdProblem.courant.offset == 24
     assert _lib.FdtdProblem.src_wave.offset % 8 == 0
-    # the loss kind follows the design box; the struct is padded to its 8-byte alignment
-    assert _lib.FdtdProblem.loss.offset == _lib.FdtdProblem.des_hi.offset + 12
-    assert ctypes.sizeof(_lib.FdtdProblem) == (_lib.FdtdProblem.loss.offset + 4 + 7) // 8 * 8
+    # the loss kind and the magnetic current follow the design box (pointers 8-byte aligned)
+    P_ = _lib.FdtdProblem
+    assert P_.loss.offset == P_.des_hi.offset + 12
+    assert P_.msrc_comp.offset == P_.loss.offset + 4 and P_.msrc_hi.offset == P_.msrc_lo.offset + 12
+    assert P_.msrc_wave.offset == (P_.msrc_hi.offset + 12 + 7) // 8 * 8
+    assert P_.msrc_profile.offset == P_.msrc_wave.offset + 8
+    assert ctypes.sizeof(P_) == P_.msrc_profile.offset + 8
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5", "tiny", "ragged"])
@@ -95,6 +99,9 @@ def test_validation_errors_before_any_device_work():
     assert _call_forward(replace(base, steps=0)) == _lib.FDTD_EINVAL
     assert _call_forward(replace(base, loss=4)) == _lib.FDTD_EINVAL       # unknown loss kind
     assert _call_forward(replace(base, loss=-1)) == _lib.FDTD_EINVAL
+    pw = w.with_tfsf_plane_wave(base, 5, 8.0)
+    assert _call_forward(replace(pw, msrc_lo=(0, 3, 4))) == _lib.FDTD_EREGION   # sheet into the PML
+    assert _call_forward(replace(pw, msrc_comp=3)) == _lib.FDTD_EINVAL
     assert _call_forward(base, k=0) == _lib.FDTD_ESTORE
     assert _call_forward(base, dtype="fp8_e4m3_scaled", k=4) == _lib.FDTD_EINVAL
 

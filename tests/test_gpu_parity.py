@@ -295,3 +295,38 @@ def test_flux_compressed_against_oracle_compressed():
     cos = metrics.cosine_similarity(out["grad"], g)
     say("  fp8 k=4 flux: cosine vs oracle-compressed %.8f" % cos)
     assert cos >= 0.9999
+
+
+# --------------------------------------------------------------------------- plane-wave (TFSF) source
+
+TFSF_CASES = {
+    "tiny_pw_flux": lambda: w.tiny_pw(),
+    "c1_pw_energy": lambda: w.with_tfsf_plane_wave(w.c1(), 10, 20.0),
+    "periodic_pw_flux": lambda: replace(w.with_tfsf_plane_wave(_periodic_problem(), 4, 10.0, 0.6), loss=3),
+}
+
+
+@pytest.mark.parametrize("case", list(TFSF_CASES))
+def test_tfsf_forward_and_gradient(case):
+    require_gpu()
+    prob = TFSF_CASES[case]()
+    say("plane-wave source", case)
+    out = gpu_run(prob)
+    st, losses, _ = yee.run_forward(yee.Solver(prob, match_fp32=True))
+    assert rel(out["E"], st.E) <= 1e-5 and rel(out["H"], st.H) <= 1e-5
+    assert abs(out["loss"] - losses.sum()) <= 1e-5 * np.sum(np.abs(losses))
+    L, g = adjoint.grad_time_reversal(prob, "fp64", 1, match_fp32=True)
+    r = rel(out["grad"], g)
+    cos = metrics.cosine_similarity(out["grad"], g)
+    say("  rel-L2 %.3e cosine %.12f" % (r, cos))
+    assert r <= 1e-4 and cos >= 1 - 1e-8
+
+
+def test_tfsf_compressed_against_oracle_compressed():
+    require_gpu()
+    prob = w.with_tfsf_plane_wave(w.c1(), 10, 20.0)
+    out = gpu_run(prob, "bf16", 3)
+    _, g = adjoint.grad_time_reversal(prob, ORACLE_MODE["bf16"], 3, match_fp32=True)
+    cos = metrics.cosine_similarity(out["grad"], g)
+    say("  bf16 k=3 plane wave: cosine vs oracle-compressed %.8f" % cos)
+    assert cos >= 0.9999

@@ -64,6 +64,13 @@ class Problem:
     eps: np.ndarray = field(default_factory=lambda: np.zeros((0, 0, 0), np.float32))
     wavelength: float = 0.0      # informational (cells)
     loss: int = 0                # 0: sum of |E|^2 on the detector; 1, 2, 3: Poynting flux along x, y, z
+    # optional magnetic current sheet M (dH/dt = -curl E - M), e.g. the H half of a
+    # total-field/scattered-field plane-wave source; empty box = none
+    msrc_comp: int = 0
+    msrc_lo: Box = (0, 0, 0)
+    msrc_hi: Box = (0, 0, 0)
+    msrc_wave: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float32))
+    msrc_profile: np.ndarray = field(default_factory=lambda: np.zeros((0, 0, 0), np.float32))
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -119,6 +126,58 @@ def time_step(courant: float) -> float:
     step size independently.
     """
     return courant / math.sqrt(3.0)
+
+
+def incident_line(steps: int, courant: float, eps_bg: float, wavelength: float, bandwidth: float = 0.4,
+                  amplitude: float = 1.0, lead: int = 20):
+    """Incident plane wave for a total-field/scattered-field sheet, from a 1-D Yee line.
+
+    An x-polarised wave travelling along +z in a uniform medium eps_bg obeys, in
+    the 3-D grid, exactly the 1-D recurrence run here (same dt and cell):
+        Hy[k] -= dt (Ex[k+1] - Ex[k]);   Ex[k] -= (dt / eps_bg) (Hy[k] - Hy[k-1]) + (dt / eps_bg) J
+    driven by a soft current J (the Gaussian pulse) `lead` cells before the sheet.
+    Returns (Ex^n at the sheet plane, Hy^{n+1/2} half a cell before it) for n < steps,
+    in float64; the line is long enough that nothing returns from its ends.
+    """
+    dt = time_step(courant)
+    half = int(steps * dt / math.sqrt(eps_bg)) + lead + 16
+    size = 2 * half + 1
+    zs, zi = half, half + lead
+    sig = gaussian_pulse(steps, dt, wavelength, bandwidth, amplitude).astype(np.float64)
+    ex = np.zeros(size)
+    hy = np.zeros(size)
+    ex_rec = np.zeros(steps)
+    hy_rec = np.zeros(steps)
+    c = dt / eps_bg
+    for n in range(steps):
+        ex_rec[n] = ex[zi]
+        hy[:-1] -= dt * (ex[1:] - ex[:-1])
+        hy_rec[n] = hy[zi - 1]
+        ex[1:] -= c * (hy[1:] - hy[:-1])
+        ex[zs] -= c * sig[n]
+    return ex_rec, hy_rec
+
+
+def with_tfsf_plane_wave(p: Problem, z0: int, wavelength: float, bandwidth: float = 0.4,
+                         amplitude: float = 1.0) -> Problem:
+    """Replace the source of `p` by a total-field/scattered-field sheet at plane z0.
+
+    An x-polarised plane wave enters the total-field region z >= z0 travelling
+    along +z over the interior x-y extent: an electric sheet J_x = -Hy_inc(z0 - 1/2)
+    on the Ex plane z0 and a magnetic sheet M_y = -Ex_inc(z0) on the Hy plane z0 - 1
+    (the corrections of the two updates that straddle the plane).  Nothing is
+    emitted into z < z0 where the wave is a plane wave of the background eps at
+    the sheet.
+    """
+    P = p.pml
+    lo, hi = (P, P), (p.nx - P, p.ny - P)
+    eps_bg = float(p.eps[z0, p.ny // 2, p.nx // 2])
+    ex_inc, hy_inc = incident_line(p.steps, p.courant, eps_bg, wavelength, bandwidth, amplitude)
+    shape = (1, hi[1] - lo[1], hi[0] - lo[0])
+    return replace(p, src_comp=0, src_lo=(lo[0], lo[1], z0), src_hi=(hi[0], hi[1], z0 + 1),
+                   src_wave=(-hy_inc).astype(np.float32), src_profile=np.ones(shape, np.float32),
+                   msrc_comp=1, msrc_lo=(lo[0], lo[1], z0 - 1), msrc_hi=(hi[0], hi[1], z0),
+                   msrc_wave=(-ex_inc).astype(np.float32), msrc_profile=np.ones(shape, np.float32))
 
 
 # ----------------------------------------------------------------------------
@@ -215,6 +274,20 @@ def c5_crop(seed: int = 0, steps: int = 2000) -> Problem:
                         seed=seed)
 
 
+def c2pw(seed: int = 0, steps: int = 1000, wavelength: float = 20.0) -> Problem:
+    """c2 driven by a total-field/scattered-field plane wave entering at z = 24, with the
+    Poynting flux through the detector plane z = 110 as the objective (transmission)."""
+    p = c2(seed=seed, steps=steps, wavelength=wavelength)
+    p = with_tfsf_plane_wave(p, 24, wavelength)
+    return replace(p, name="c2pw_128cube_tfsf_flux", loss=3)
+
+
+def tiny_pw(seed: int = 0, steps: int = 60) -> Problem:
+    """tiny with a total-field/scattered-field plane wave entering at z = 4 and z-flux objective."""
+    p = tiny(seed=seed, steps=steps)
+    return replace(with_tfsf_plane_wave(p, 4, 8.0, 0.6), name="tiny_pw", loss=3)
+
+
 def tiny(seed: int = 0, n: Box = (12, 12, 12), pml: int = 3, steps: int = 60,
          wavelength: float = 8.0) -> Problem:
     """Small grid for brute-force checks: 12^3, 3-cell CPML, 3^3 design around the source."""
@@ -245,7 +318,7 @@ def ragged(seed: int = 0, steps: int = 40) -> Problem:
 
 PRESETS = {
     "c1": c1, "c2": c2, "c3p": c3p, "c4": c4, "c5": c5, "c5crop": c5_crop,
-    "tiny": tiny, "ragged": ragged,
+    "tiny": tiny, "ragged": ragged, "c2pw": c2pw, "tiny_pw": tiny_pw,
 }
 
 
