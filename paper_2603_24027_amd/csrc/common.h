@@ -396,23 +396,26 @@ __device__ inline float nb_minus(const float* f, long long idx, int i, int n, lo
 }
 
 // One step's loss term at one detector cell from E^{n+1} and H^{n+1/2} at that index:
-// |E|^2 (loss 0) or (E x H) along x, y, z (loss 1, 2, 3).
+// |E|^2 (loss 0) or (E x H) along x, y, z (loss 1, 2, 3).  Written without run-time
+// array indices so that e and h stay in registers.
 __device__ inline double loss_term(int loss, const float e[3], const float h[3]) {
-    if (loss == 0) return (double)e[0] * e[0] + (double)e[1] * e[1] + (double)e[2] * e[2];
-    const int a = loss % 3, b = (loss + 1) % 3;      // axis loss-1: components axis+1, axis+2
-    return (double)e[a] * h[b] - (double)e[b] * h[a];
+    switch (loss) {
+        case 1: return (double)e[1] * h[2] - (double)e[2] * h[1];
+        case 2: return (double)e[2] * h[0] - (double)e[0] * h[2];
+        case 3: return (double)e[0] * h[1] - (double)e[1] * h[0];
+        default: return (double)e[0] * e[0] + (double)e[1] * e[1] + (double)e[2] * e[2];
+    }
 }
 
 // Its derivatives (dL/dE^{n+1}, dL/dH^{n+1/2}) at that cell.
 __device__ inline void loss_seeds(int loss, const float e[3], const float h[3], float gE[3], float gH[3]) {
     gE[0] = gE[1] = gE[2] = gH[0] = gH[1] = gH[2] = 0.0f;
-    if (loss == 0) {
-        gE[0] = 2.0f * e[0]; gE[1] = 2.0f * e[1]; gE[2] = 2.0f * e[2];
-        return;
+    switch (loss) {
+        case 1: gE[1] = h[2]; gE[2] = -h[1]; gH[2] = e[1]; gH[1] = -e[2]; break;
+        case 2: gE[2] = h[0]; gE[0] = -h[2]; gH[0] = e[2]; gH[2] = -e[0]; break;
+        case 3: gE[0] = h[1]; gE[1] = -h[0]; gH[1] = e[0]; gH[0] = -e[1]; break;
+        default: gE[0] = 2.0f * e[0]; gE[1] = 2.0f * e[1]; gE[2] = 2.0f * e[2]; break;
     }
-    const int a = loss % 3, b = (loss + 1) % 3;
-    gE[a] = h[b]; gE[b] = -h[a];
-    gH[b] = e[a]; gH[a] = -e[b];
 }
 
 // dt / eps of the E update; the forward step, its reversal and its adjoint all use

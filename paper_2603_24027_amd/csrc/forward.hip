@@ -84,7 +84,7 @@ __device__ __forceinline__ uint32_t src_plane(const Grid& g, int k, uint32_t lan
 }
 
 // Straight-line loads of plane k's inputs (out-of-domain and out-of-slab values read as 0).
-template <int TY>
+template <int TY, bool MS>
 __device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, const FwdLanes& L,
                                               const FwdCtx<TY>& c, int k, PlaneIn& d) {
     const uint32_t nb = (uint32_t)c.N << 2;
@@ -100,10 +100,14 @@ __device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, c
     uint32_t ss;
     const uint32_t vs = src_plane(g, k, L.src, ss);
     d.sp = bldv(b.src, vs, ss);
-    uint32_t ms;
-    const bool mz = box_plane(g.msrc_lo, g.msrc_hi, k, ms);
-    d.mp = bldv(b.msrc, mz ? L.m : OOB, ms);
-    d.mph = bldv(b.msrc, mz ? L.mh : OOB, ms);
+    if constexpr (MS) {   // a magnetic-current sheet exists (a separate instantiation)
+        uint32_t ms;
+        const bool mz = box_plane(g.msrc_lo, g.msrc_hi, k, ms);
+        d.mp = bldv(b.msrc, mz ? L.m : OOB, ms);
+        d.mph = bldv(b.msrc, mz ? L.mh : OOB, ms);
+    } else {
+        d.mp = d.mph = 0.0f;
+    }
     const PsiPlane pH = psi_plane(g, 0, k, b.hin), pE = psi_plane(g, 1, k, 0);
     bld_psi_v(b.psi, L.po, pH, d.ph);
     bld_psi_v(b.psi, L.po, pE, d.pe);
@@ -114,7 +118,7 @@ __device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, c
 // and halo cells, then E^{n+1}(k) on the own cell.  `in` holds the plane's inputs,
 // loaded one plane ahead.  All stores are unconditional buffer stores (dropped for
 // idle lanes and cells outside a slab).
-template <int TY, int REC, int CZ>
+template <int TY, int REC, int CZ, bool MS>
 __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const FwdLanes& L, const FwdCtx<TY>& c,
                                           float (*sE)[3][TY + 2][EXT], float (*sH)[TY + 1][TX + 1],
                                           const CoefTile<TY, CZ>& ct, int lz, int cur, int k,
@@ -145,7 +149,7 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
         if (L.ysl) cpml_y(cf_y(ct, 1, row + 1), t, ph);
         if (pH.zs) cpml_z(cf_z(ct, 1, lz), t, ph);
         const float dt = g.dt;
-        const float m = dt * mwave * in.mp;     // magnetic current (0 outside its sheet)
+        const float m = MS ? dt * mwave * in.mp : 0.0f;     // magnetic current (0 outside its sheet)
         h[0] = c.live ? in.h0[0] - dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f) : 0.0f;
         h[1] = c.live ? in.h0[1] - dt * (t[2] - t[3]) - (g.msrc_comp == 1 ? m : 0.0f) : 0.0f;
         h[2] = c.live ? in.h0[2] - dt * (t[4] - t[5]) - (g.msrc_comp == 2 ? m : 0.0f) : 0.0f;
@@ -180,7 +184,7 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
             h_terms<TY>(sE[cur], sE[nxt], c.hex, c.hey, t);
             cpml_apply(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, lz), t, phh);
             const float dt = g.dt;
-            const float m = dt * mwave * in.mph;
+            const float m = MS ? dt * mwave * in.mph : 0.0f;
             hh[0] = in.hh0[0] - dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f);
             hh[1] = in.hh0[1] - dt * (t[2] - t[3]) - (g.msrc_comp == 1 ? m : 0.0f);
             hh[2] = in.hh0[2] - dt * (t[4] - t[5]) - (g.msrc_comp == 2 ? m : 0.0f);
@@ -229,7 +233,7 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
 #ifndef FDTD_FWD_WAVES
 #define FDTD_FWD_WAVES 1
 #endif
-template <int TY, int REC, int CZ>
+template <int TY, int REC, int CZ, bool MS>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FWD_WAVES))) void k_fwd_step(
     Grid g, Tiling tl, const float* __restrict__ F0, float* __restrict__ F1, float* __restrict__ psi, int hcopy,
     const float* __restrict__ eps, float wave, float mwave, double* __restrict__ partials,
@@ -270,8 +274,9 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     else if constexpr (REC >= 0) b.rec = make_rsrc((char*)store + (long long)slice * g.slice_stride, (uint32_t)g.slice_stride);
     const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
     b.src = make_rsrc(g.src_profile, (uint32_t)(sxn * syn * (g.src_hi[2] - g.src_lo[2])) * 4u);
-    b.msrc = make_rsrc(g.msrc_profile, (uint32_t)((g.msrc_hi[0] - g.msrc_lo[0]) * (g.msrc_hi[1] - g.msrc_lo[1]) *
-                                                  (g.msrc_hi[2] - g.msrc_lo[2])) * 4u);
+    if constexpr (MS)
+        b.msrc = make_rsrc(g.msrc_profile, (uint32_t)((g.msrc_hi[0] - g.msrc_lo[0]) * (g.msrc_hi[1] - g.msrc_lo[1]) *
+                                                      (g.msrc_hi[2] - g.msrc_lo[2])) * 4u);
 
     // columns this thread touches: its own, one position of the LDS ring, one halo H cell
     c.own = make_col(g, c.x, c.y);
@@ -324,10 +329,13 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
         PsiLane lm = Ln.po;
         if (zm < 0) lm.x = lm.y = lm.z = OOB;
         bld_psi_v(b.psi, lm, pm, p);
-        uint32_t msm;
-        const bool mzm = zm >= 0 && box_plane(g.msrc_lo, g.msrc_hi, zm, msm);
-        const float mpm = bldv(b.msrc, mzm ? Ln.m : OOB, msm);
-        load_plane_in<TY>(g, b, Ln, c, k0, pin[0]);
+        float mpm = 0.0f;
+        if constexpr (MS) {
+            uint32_t msm;
+            const bool mzm = zm >= 0 && box_plane(g.msrc_lo, g.msrc_hi, zm, msm);
+            mpm = bldv(b.msrc, mzm ? Ln.m : OOB, msm);
+        }
+        load_plane_in<TY, MS>(g, b, Ln, c, k0, pin[0]);
         #pragma unroll
         for (int q = 0; q < 3; ++q) {
             sE[0][q][row + 1][lane + 1] = a[q];
@@ -352,9 +360,9 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     for (int kk = 0; kk < CZ; ++kk) {
         const int k = k0 + kk;
         if (kk + 1 < CZ)   // inputs of the next plane (an unused valid plane past the end of the grid)
-            load_plane_in<TY>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+            load_plane_in<TY, MS>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
         if (k < k1)
-            fwd_plane<TY, REC, CZ>(g, b, Ln, c, sE, sH, ct, kk + 1, (kk + 1) & 1, k, pin[kk & 1], eo, hx_prev,
+            fwd_plane<TY, REC, CZ, MS>(g, b, Ln, c, sE, sH, ct, kk + 1, (kk + 1) & 1, k, pin[kk & 1], eo, hx_prev,
                                    hy_prev, e2, wave, mwave);
     }
     // detector partial of this tile (tiles intersecting the detector only; uniform per block)
@@ -416,33 +424,43 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
     if (threadIdx.x == 0) *loss = red[0];
 }
 
-template <int TY, int CZ>
+template <int TY, int CZ, bool MS>
 static void launch_fwd_step_t(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
                               const float* eps, float wave, float mwave, double* partials, void* store,
                               float* staging, int slice, hipStream_t s) {
     const dim3 grid(t.count), block(TX, TY);
     if (slice < 0 || g.P == 0) {
-        launch_kernel(K_FWD_STEP, k_fwd_step<TY, -1, CZ>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
+        launch_kernel(K_FWD_STEP, k_fwd_step<TY, -1, CZ, MS>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
                       mwave, partials, store, staging, slice);
         return;
     }
     with_dtype(g.dtype, [&]<int DT>() {
-        launch_kernel(K_FWD_STEP, k_fwd_step<TY, DT, CZ>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
+        launch_kernel(K_FWD_STEP, k_fwd_step<TY, DT, CZ, MS>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
                       mwave, partials, store, staging, slice);
     });
+}
+
+template <int TY, int CZ>
+static void launch_fwd_step_m(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
+                              const float* eps, float wave, float mwave, double* partials, void* store,
+                              float* staging, int slice, hipStream_t s) {
+    if (g.msrc_hi[0] > g.msrc_lo[0])
+        launch_fwd_step_t<TY, CZ, true>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
+    else
+        launch_fwd_step_t<TY, CZ, false>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
 }
 
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
                      const float* eps, float wave, float mwave, double* partials, void* store, float* staging,
                      int slice, hipStream_t s) {
     if (t.ty == 4 && t.cz == 4)
-        launch_fwd_step_t<4, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
+        launch_fwd_step_m<4, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
     else if (t.ty == 4)
-        launch_fwd_step_t<4, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
+        launch_fwd_step_m<4, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
     else if (t.cz == 4)
-        launch_fwd_step_t<8, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
+        launch_fwd_step_m<8, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
     else
-        launch_fwd_step_t<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
+        launch_fwd_step_m<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
 }
 
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s) {

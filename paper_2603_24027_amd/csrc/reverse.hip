@@ -412,7 +412,7 @@ __device__ inline bool src_z(const Grid& g, int z, uint32_t& s) {
 }
 __device__ inline bool z_interior(const Grid& g, int z) { return z >= g.P && z < g.nz - g.P; }
 
-template <int TY>
+template <int TY, bool MS>
 __device__ __forceinline__ void load_rev_in(const Grid& g, const RevBufs& b, const RevLanes& L, const RevCtx<TY>& c,
                                             int k, RevIn& d) {
     const uint32_t nb = (uint32_t)c.N << 2;
@@ -430,9 +430,13 @@ __device__ __forceinline__ void load_rev_in(const Grid& g, const RevBufs& b, con
     const bool sz = z1 >= 0 && src_z(g, z1, ss);
     d.sp = bldv(b.src, sz ? L.src : OOB, ss);
     d.xsp = bldv(b.src, sz ? L.xsrc : OOB, ss);
-    uint32_t ms;
-    const bool mz = box_plane(g.msrc_lo, g.msrc_hi, k, ms);
-    d.mp = bldv(b.msrc, mz ? L.m : OOB, ms);
+    if constexpr (MS) {   // a magnetic-current sheet exists (a separate instantiation)
+        uint32_t ms;
+        const bool mz = box_plane(g.msrc_lo, g.msrc_hi, k, ms);
+        d.mp = bldv(b.msrc, mz ? L.m : OOB, ms);
+    } else {
+        d.mp = 0.0f;
+    }
     // the shell values were written into the output buffer before this sweep
     const bool zh = z1 >= 0 && z1 == g.nz - g.P;
     bld3v(b.F1, zi ? L.shk : (zh ? L.shz : OOB), s1, nb, d.sh);
@@ -541,7 +545,7 @@ __device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const R
 #ifndef FDTD_REV_WAVES
 #define FDTD_REV_WAVES 1
 #endif
-template <int TY, int CZ>
+template <int TY, int CZ, bool MS>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_REV_WAVES))) void k_prim_rev(
     Grid g, Tiling tl, Box bx, const float* __restrict__ F0, float* __restrict__ F1, const float* __restrict__ eps,
     float* __restrict__ Eb0, float wave, float mwave, double* __restrict__ grad) {
@@ -571,8 +575,9 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     b.eps = make_rsrc(eps, (uint32_t)(c.plane * g.nz) * 4u);
     b.src = make_rsrc(g.src_profile, (uint32_t)((g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1]) *
                                                 (g.src_hi[2] - g.src_lo[2])) * 4u);
-    b.msrc = make_rsrc(g.msrc_profile, (uint32_t)((g.msrc_hi[0] - g.msrc_lo[0]) * (g.msrc_hi[1] - g.msrc_lo[1]) *
-                                                  (g.msrc_hi[2] - g.msrc_lo[2])) * 4u);
+    if constexpr (MS)
+        b.msrc = make_rsrc(g.msrc_profile, (uint32_t)((g.msrc_hi[0] - g.msrc_lo[0]) * (g.msrc_hi[1] - g.msrc_lo[1]) *
+                                                      (g.msrc_hi[2] - g.msrc_lo[2])) * 4u);
     c.own = make_col(g, c.x, c.y);
     c.rlx = c.rly = -1;
     c.ring.xy = -1;
@@ -630,7 +635,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
         float sh[3], xsh[3];
         bld3v(b.F1, zi ? Ln.shk : (zh ? Ln.shz : OOB), s0, nb, sh);
         bld3v(b.F1, zi ? Ln.xshk : (zh ? Ln.xshz : OOB), s0, nb, xsh);
-        load_rev_in<TY>(g, b, Ln, c, k0, pin[0]);
+        load_rev_in<TY, MS>(g, b, Ln, c, k0, pin[0]);
         ep = ep == 0.0f ? 1.0f : ep;
         xep = xep == 0.0f ? 1.0f : xep;
         #pragma unroll
@@ -649,7 +654,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     #pragma unroll
     for (int kk = 0; kk < CZ; ++kk) {
         const int k = k0 + kk;
-        if (kk + 1 < CZ) load_rev_in<TY>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+        if (kk + 1 < CZ) load_rev_in<TY, MS>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
         if (k >= k1) continue;
         const int hc = (kk + 1) & 1, hn = 1 - hc;      // H plane k in sH[hc]
         const int ec = kk & 1, en = 1 - ec;            // E^n plane k in sE[ec]
@@ -674,7 +679,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
             h[0] = sH[hc][0][row + 1][lane + 1] + dt * ((sE[ec][2][row + 1][lane] - ezc) - (sE[en][1][row][lane] - eyc));
             h[1] = sH[hc][1][row + 1][lane + 1] + dt * ((sE[en][0][row][lane] - exc) - (sE[ec][2][row][lane + 1] - ezc));
             h[2] = sH[hc][2][row + 1][lane + 1] + dt * ((sE[ec][1][row][lane + 1] - eyc) - (sE[ec][0][row + 1][lane] - exc));
-            const float m = dt * mwave * in.mp;     // the magnetic current of the step, 0 off its sheet
+            const float m = MS ? dt * mwave * in.mp : 0.0f;   // the step's magnetic current, 0 off its sheet
             h[0] += g.msrc_comp == 0 ? m : 0.0f;
             h[1] += g.msrc_comp == 1 ? m : 0.0f;
             h[2] += g.msrc_comp == 2 ? m : 0.0f;
@@ -737,8 +742,12 @@ void launch_adj_step(const Grid& g, const Tiling& t, const float* A0, float* A1,
 template <int TY, int CZ>
 static void launch_prim_rev_t(const Grid& g, const Tiling& t, const Box& b, const float* F0, float* F1,
                               const float* eps, float* Eb0, float wave, float mwave, double* grad, hipStream_t s) {
-    launch_kernel(K_PRIM_REV, k_prim_rev<TY, CZ>, dim3(t.count), dim3(TX, TY), s, g, t, b, F0, F1, eps, Eb0, wave,
-                  mwave, grad);
+    if (g.msrc_hi[0] > g.msrc_lo[0])
+        launch_kernel(K_PRIM_REV, k_prim_rev<TY, CZ, true>, dim3(t.count), dim3(TX, TY), s, g, t, b, F0, F1, eps, Eb0,
+                      wave, mwave, grad);
+    else
+        launch_kernel(K_PRIM_REV, k_prim_rev<TY, CZ, false>, dim3(t.count), dim3(TX, TY), s, g, t, b, F0, F1, eps,
+                      Eb0, wave, mwave, grad);
 }
 
 void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
