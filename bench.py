@@ -36,6 +36,7 @@ WORKLOADS = {
     "c4": ("c4", {}, "fp32", 1),
     "c5": ("c5", {}, "fp32", 1),
     "c3p": ("c3p", {}, "fp32", 1),
+    "c2pw": ("c2pw", {}, "fp32", 1),          # plane-wave source, z-flux objective
 }
 KERNEL_SOURCES = ["paper_2603_24027_amd/csrc/common.h", "paper_2603_24027_amd/csrc/march.h",
                   "paper_2603_24027_amd/csrc/forward.hip", "paper_2603_24027_amd/csrc/reverse.hip",

@@ -73,7 +73,7 @@ struct FwdLanes {
 // (own cell and the halo cell), eps, the source profile (0 outside the source box)
 // and the PML auxiliaries of plane k.
 struct PlaneIn {
-    float e1[3], er[3], h0[3], hh0[3], ep, sp, mp, mph;   // mp, mph: magnetic-current profile (own, halo)
+    float e1[3], er[3], h0[3], hh0[3], ep, sp;
     float ph[6], pe[6], phh[6];
 };
 
@@ -100,14 +100,6 @@ __device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, c
     uint32_t ss;
     const uint32_t vs = src_plane(g, k, L.src, ss);
     d.sp = bldv(b.src, vs, ss);
-    if constexpr (MS) {   // a magnetic-current sheet exists (a separate instantiation)
-        uint32_t ms;
-        const bool mz = box_plane(g.msrc_lo, g.msrc_hi, k, ms);
-        d.mp = bldv(b.msrc, mz ? L.m : OOB, ms);
-        d.mph = bldv(b.msrc, mz ? L.mh : OOB, ms);
-    } else {
-        d.mp = d.mph = 0.0f;
-    }
     const PsiPlane pH = psi_plane(g, 0, k, b.hin), pE = psi_plane(g, 1, k, 0);
     bld_psi_v(b.psi, L.po, pH, d.ph);
     bld_psi_v(b.psi, L.po, pE, d.pe);
@@ -141,6 +133,16 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
     }
     __syncthreads();
     // ---- first half: H^{n+1/2} on the own cell and the halo cell ----
+    float mp = 0.0f, mph = 0.0f;
+    if constexpr (MS) {
+        // the magnetic-current sheet (a separate instantiation): only planes that carry it
+        // load it, under a branch that is uniform per block and waits for its own loads
+        uint32_t ms;
+        if (box_plane(g.msrc_lo, g.msrc_hi, k, ms)) {
+            mp = bldv(b.msrc, L.m, ms);
+            mph = bldv(b.msrc, L.mh, ms);
+        }
+    }
     float h[3];
     {
         float t[6];
@@ -149,7 +151,7 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
         if (L.ysl) cpml_y(cf_y(ct, 1, row + 1), t, ph);
         if (pH.zs) cpml_z(cf_z(ct, 1, lz), t, ph);
         const float dt = g.dt;
-        const float m = MS ? dt * mwave * in.mp : 0.0f;     // magnetic current (0 outside its sheet)
+        const float m = MS ? dt * mwave * mp : 0.0f;     // magnetic current (0 outside its sheet)
         h[0] = c.live ? in.h0[0] - dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f) : 0.0f;
         h[1] = c.live ? in.h0[1] - dt * (t[2] - t[3]) - (g.msrc_comp == 1 ? m : 0.0f) : 0.0f;
         h[2] = c.live ? in.h0[2] - dt * (t[4] - t[5]) - (g.msrc_comp == 2 ? m : 0.0f) : 0.0f;
@@ -184,7 +186,7 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
             h_terms<TY>(sE[cur], sE[nxt], c.hex, c.hey, t);
             cpml_apply(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, lz), t, phh);
             const float dt = g.dt;
-            const float m = MS ? dt * mwave * in.mph : 0.0f;
+            const float m = MS ? dt * mwave * mph : 0.0f;
             hh[0] = in.hh0[0] - dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f);
             hh[1] = in.hh0[1] - dt * (t[2] - t[3]) - (g.msrc_comp == 1 ? m : 0.0f);
             hh[2] = in.hh0[2] - dt * (t[4] - t[5]) - (g.msrc_comp == 2 ? m : 0.0f);
