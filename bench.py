@@ -37,7 +37,12 @@ WORKLOADS = {
     "c5": ("c5", {}, "fp32", 1),
     "c3p": ("c3p", {}, "fp32", 1),
     "c2pw": ("c2pw", {}, "fp32", 1),          # plane-wave source, z-flux objective
+    "c5crop": ("c5crop", {}, "fp32", 1),      # the c5 recipe on 128^3, 2000 steps
 }
+# workload -> its 128^3 crop, whose exact gradient the FP64 oracle stores (tests/golden)
+CROPS = {"c5": "c5crop"}
+# storage settings timed beside the plain FP32 one (the first is reported as "compressed")
+COMPRESSED = {"c5": [("fp8_e4m3_scaled", 16), ("bf16", 4)]}
 KERNEL_SOURCES = ["paper_2603_24027_amd/csrc/common.h", "paper_2603_24027_amd/csrc/march.h",
                   "paper_2603_24027_amd/csrc/forward.hip", "paper_2603_24027_amd/csrc/reverse.hip",
                   "paper_2603_24027_amd/csrc/api.hip"]
@@ -56,19 +61,23 @@ def algorithmic_bytes(prob, design_cells: int):
 
     fwd_step and adj_step sweep every cell: 52 B (read the six field components
     and eps, write the six) plus 32 B per PML slab cell and axis (four auxiliaries
-    read and written).  prim_rev sweeps the interior: 52 B per interior cell plus
-    the FP64 gradient (16 B read-modify-write) and the adjoint E it reads (12 B)
-    per design cell.
+    read and written); the adjoint launch also writes the next step's interface
+    shell (two components per face cell of the interior's six faces, each read
+    from an FP32 store and written: 16 B per face cell).  prim_rev sweeps the
+    interior: 52 B per interior cell plus the FP64 gradient (16 B
+    read-modify-write) and the adjoint E it reads (12 B) per design cell.
     """
     P = prob.pml
     N = prob.nx * prob.ny * prob.nz
     NI = (prob.nx - 2 * P) * (prob.ny - 2 * P) * (prob.nz - 2 * P)
     NP = N - NI
     S = 2 * P * (prob.ny * prob.nz + prob.nx * prob.nz + prob.nx * prob.ny)
+    mx, my, mz = prob.nx - 2 * P, prob.ny - 2 * P, prob.nz - 2 * P
+    shell = 2 * (my * mz + mx * mz + mx * my) if P > 0 else 0
     return {
         "fwd_step": 52 * N + 32 * S,
         "prim_rev": 52 * NI + 28 * design_cells,
-        "adj_step": 52 * N + 32 * S,
+        "adj_step": 52 * N + 32 * S + 16 * shell,
         # single-sweep lower bound of one time step, fwd + rev (52 B forward; 100 B interior /
         # 52 B PML reverse; PML auxiliaries; FP64 gradient)
         "step_min": 52 * N + 100 * NI + 52 * NP + 64 * S + 16 * design_cells,
@@ -359,16 +368,24 @@ def main():
                           if n not in kernels},
     }
 
+    c_obj = None
     if not args.no_compressed:
-        c_el, c_obj = timed_run("fp8_e4m3_scaled", 16, args.steps, args.warmup)
-        progress("compressed timed region: %.3f s" % c_el)
-        out["compressed"] = {"store_dtype": "fp8_e4m3_scaled", "k": 16,
-                             "value": round(cells * T * args.steps / c_el / 1e6, 1),
-                             "ms_per_step": round(c_el / args.steps * 1e3, 3),
-                             "t_fwd_ms": round(fwd_rev_ms[("fp8_e4m3_scaled", 16)][0], 3),
-                             "t_rev_ms": round(fwd_rev_ms[("fp8_e4m3_scaled", 16)][1], 3),
-                             "boundary_store_GB": c_obj.info.payload_bytes / 1e9,
-                             "storage_reduction": gobj.info.payload_bytes / c_obj.info.payload_bytes}
+        for i, (cd, ck) in enumerate(COMPRESSED.get(args.workload, [("fp8_e4m3_scaled", 16)])):
+            c_el, obj = timed_run(cd, ck, args.steps, args.warmup)
+            progress("compressed timed region (%s k=%d): %.3f s" % (cd, ck, c_el))
+            rec = {"store_dtype": cd, "k": ck,
+                   "value": round(cells * T * args.steps / c_el / 1e6, 1),
+                   "ms_per_step": round(c_el / args.steps * 1e3, 3),
+                   "t_fwd_ms": round(fwd_rev_ms[(cd, ck)][0], 3),
+                   "t_rev_ms": round(fwd_rev_ms[(cd, ck)][1], 3),
+                   "boundary_store_GB": obj.info.payload_bytes / 1e9,
+                   "storage_reduction": gobj.info.payload_bytes / obj.info.payload_bytes}
+            if i == 0:
+                out["compressed"] = rec
+                c_obj = obj
+            else:
+                out.setdefault("compressed_more", []).append(rec)
+            del obj
 
     if not args.no_cpu_baseline:
         progress("oracle baseline on the host, %d steps" % args.cpu_sample_steps)
@@ -381,10 +398,25 @@ def main():
     exact = oracle_gradient(prob.name, 0)
     if exact is not None:
         errs = {"%s_k%d" % (dtype, k): gobj.buf.grad.cpu().numpy()}
-        if not args.no_compressed:
-            errs["fp8_e4m3_scaled_k16"] = c_obj.buf.grad.cpu().numpy()
+        if c_obj is not None:
+            errs["%s_k%d" % (c_obj.dtype, c_obj.k)] = c_obj.buf.grad.cpu().numpy()
         out["grad_err_vs_fp64_oracle"] = {
             name: {"rel_l2": rel_l2(g, exact), "cosine": cosine(g, exact)} for name, g in errs.items()}
+    if args.workload in CROPS:
+        # gradient error of every storage setting on the 128^3 crop of this workload's recipe
+        cprob = w.make(CROPS[args.workload], seed=0)
+        cexact = oracle_gradient(cprob.name, 0)
+        if cexact is not None:
+            ce = torch.from_numpy(cprob.eps).to(dev)
+            res = {"workload": cprob.name}
+            for cd, ck in [("fp32", 1)] + COMPRESSED.get(args.workload, []):
+                obj = pk.Gradient(cprob, cd, ck, device=dev)
+                obj.forward(ce)
+                gr = obj.backward().cpu().numpy()
+                res["%s_k%d" % (cd, ck)] = {"rel_l2": rel_l2(gr, cexact), "cosine": cosine(gr, cexact),
+                                            "boundary_store_GB": obj.info.payload_bytes / 1e9}
+                del obj
+            out["crop_grad_err_vs_fp64_oracle"] = res
     print(json.dumps(out))
 
 

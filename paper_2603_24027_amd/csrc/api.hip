@@ -54,7 +54,8 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
 
 struct Plan {
     Grid g;
-    Tiling fwd;            // forward and adjoint sweeps: the whole grid
+    Tiling fwd;            // forward sweep: the whole grid
+    Tiling adj;            // adjoint sweep: the whole grid
     Tiling rev;            // primal reversal: the interior plus its shell
     int box_o[3], box_n[3];
     int rev_x0;                    // x origin of the primal-reversal tiles (128-byte aligned)
@@ -201,6 +202,16 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
         pl->box_o[d] = P > 0 ? P - 1 : 0;
         pl->box_n[d] = P > 0 ? n[d] - 2 * P + 2 : n[d];
     }
+    Tiling& a = pl->adj;
+    a = t;
+    // 8-row tiles when the 4-row tiling fills the chip in one round (4 workgroups
+    // on each of 256 compute units): fewer halo rows at the same occupancy
+    const int adj_rounds4 = (t.ntx * ((p->ny + 3) / 4) * ((p->nz + 7) / 8) + 1023) / 1024;
+    a.ty = env_int("FDTD_ADJ_TILE_Y", adj_rounds4 <= 1 ? 8 : 4) == 8 ? 8 : 4;
+    a.cz = env_int("FDTD_ADJ_TILE_Z", 8) == 4 ? 4 : 8;
+    a.nty = (p->ny + a.ty - 1) / a.ty;
+    a.ntz = (p->nz + a.cz - 1) / a.cz;
+    a.count = a.ntx * a.nty * a.ntz;
     Tiling& r = pl->rev;
     r = t;
     r.ty = env_int("FDTD_REV_TILE_Y", 4) == 8 ? 8 : 4;
@@ -493,19 +504,25 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
         launch_fill(adj_psi, 2 * (long long)pl.psi_floats, 0.0f, q);
         launch_fill_f64(grad_eps, (long long)pl.info.design_cells, 0.0, q);
         const Interp none{-1, 0, 0.0f, 0.0f};
-        launch_inject_shell(g, Fp[0], store, none, interp_for(T - 1, T, k), 0, 1, q);
+        // the interface shell of the output state of reverse step n (E^n high faces,
+        // H^{n-1/2} low faces), written into buffer F before prim_rev of step n
+        auto shell_for = [&](int n, float* F) {
+            return ShellJob{F, store, interp_for(n, T, k), n >= 1 ? interp_for(n - 1, T, k) : none, 1, n >= 1 ? 1 : 0};
+        };
+        launch_inject_shell(g, ShellJob{Fp[0], store, none, interp_for(T - 1, T, k), 0, 1}, q);   // H^{T-1/2}
+        launch_inject_shell(g, shell_for(T - 1, Fp[1]), q);
         for (int n = T - 1; n >= 0; --n) {
             const int st = T - 1 - n;
             float* po = Fp[st & 1];
             float* pn = Fp[(st + 1) & 1];
             float* ao = Fa[st & 1];
             float* an = Fa[(st + 1) & 1];
-            // the interface shell of the output state (E^n high faces, H^{n-1/2} low faces), then
-            // the interior reversal, which reads the E part of that shell
-            launch_inject_shell(g, pn, store, interp_for(n, T, k), n >= 1 ? interp_for(n - 1, T, k) : none, 1, n >= 1,
-                                q);
+            // the interior reversal reads the E part of pn's shell; the adjoint launch then
+            // writes the shell of step n-1 into po, which the reversal has finished reading
             launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], mwave(n), grad_eps, q);
-            launch_adj_step(g, pl.fwd, ao, an, eps, adj_psi, st & 1, q);
+            ShellJob next{};
+            if (n >= 1) next = shell_for(n - 1, po);
+            launch_adj_step(g, pl.adj, ao, an, eps, adj_psi, st & 1, n >= 1 ? &next : nullptr, q);
         }
         if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, q);
     };

@@ -281,6 +281,16 @@ struct Interp {
     float w0, w1;
 };
 
+// The interface shell of one reverse step, to be written into the primal field
+// buffer F from the store: H at the low faces (interpolation qH) when do_h, E at
+// the high faces (interpolation qE) when do_e.
+struct ShellJob {
+    float* F;
+    const void* store;
+    Interp qE, qH;
+    int do_e, do_h;
+};
+
 __device__ inline float shell_value(const Grid& g, const void* store, const Interp& q, int b, long long off) {
     long long o = block_offset(g, b) + off;
     const float* scales = (const float*)((const char*)store + g.scale_off);
@@ -460,13 +470,13 @@ void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1,
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s);
 void launch_loss_final(const double* partials, int steps, int per_step, double* loss, double* series,
                        hipStream_t s);
-void launch_inject_shell(const Grid& g, float* F, const void* store, Interp qE, Interp qH, int do_e, int do_h,
-                         hipStream_t s);
+void launch_inject_shell(const Grid& g, const ShellJob& job, hipStream_t s);
 void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
                      const float* F0, float* F1, const float* eps, float* Eb0, float wave, float mwave,
                      double* grad, hipStream_t s);
+// job (may be NULL): a shell written by trailing workgroups of the same launch
 void launch_adj_step(const Grid& g, const Tiling& t, const float* A0, float* A1, const float* eps, float* psi,
-                     int pcopy, hipStream_t s);
+                     int pcopy, const ShellJob* job, hipStream_t s);
 void launch_scale_grad(double* grad, long long n, const double* scale, hipStream_t s);
 void launch_codec_roundtrip(int dtype, const float* values, long long n_blocks, long long block_len,
                             void* codes, float* scales, float* decoded, hipStream_t s);

@@ -170,16 +170,25 @@ __device__ inline void cpml_terms(const float* __restrict__ tab, int P, const Co
 // exactly the values it needs.
 // ---------------------------------------------------------------------------
 using rsrc_t = __amdgpu_buffer_rsrc_t;
+// cache-policy bits of the sweeps' buffer loads and stores (a translation unit
+// may set them before including this header); non-temporal hints (bit 1) were
+// measured 15-20 % slower on every sweep
+#ifndef FDTD_LD_AUX
+#define FDTD_LD_AUX 0
+#endif
+#ifndef FDTD_ST_AUX
+#define FDTD_ST_AUX 0
+#endif
 constexpr uint32_t OOB = 0x80000000u;          // every buffer here is smaller than 2 GiB
 
 __device__ inline rsrc_t make_rsrc(const void* p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 __device__ inline float bld(rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, FDTD_LD_AUX));
 }
 __device__ inline void bst(rsrc_t r, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, FDTD_ST_AUX);
 }
 // byte offset of element idx of component c of a 3-component field (OOB when idx < 0)
 __device__ inline uint32_t foff(int idx, int c, int N) {
@@ -282,10 +291,10 @@ __device__ inline void cpml_apply(const Cf& cx, const Cf& cy, const Cf& cz, floa
 // so that the z-march spends no vector instructions on addresses.  An OOB lane
 // offset stays out of range whatever s is added (every buffer is below 2 GiB).
 __device__ inline float bldv(rsrc_t r, uint32_t v, uint32_t s) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v, s, FDTD_LD_AUX));
 }
 __device__ inline void bstv(rsrc_t r, uint32_t v, uint32_t s, float x) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, v, s, FDTD_ST_AUX);
 }
 // three components of a field: component c at s + c * nb (nb = 4 N)
 __device__ inline void bld3v(rsrc_t r, uint32_t v, uint32_t s, uint32_t nb, float o[3]) {

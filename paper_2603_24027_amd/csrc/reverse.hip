@@ -30,6 +30,19 @@
 // auxiliaries all ping-pong), so the gradient of step n reads the adjoint
 // state before step n's transpose and the seed reads E^{n+1} before it is
 // replaced.
+//
+// The interface shell that prim_rev of step n-1 needs (E^{n-1} on the high
+// faces, H^{n-3/2} on the low ones, decoded and interpolated from the store) is
+// written into the primal buffer that prim_rev of step n has just read, by
+// extra workgroups appended to the adjoint launch of step n, which touches
+// no primal buffer; only the first reverse step needs a launch of its own.
+// Stores carry device scope (cache-policy bit sc1), as in the forward sweep: they
+// write through the XCD's L2 instead of leaving dirty lines for the writeback at
+// the end of every launch (measured: about 3 us of 64 per reverse step at 128^3).
+#ifndef FDTD_REV_ST_AUX
+#define FDTD_REV_ST_AUX 16
+#endif
+#define FDTD_ST_AUX FDTD_REV_ST_AUX
 #include "march.h"
 
 namespace fdtd {
@@ -226,20 +239,79 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
     ebc[0] = in.eb[0]; ebc[1] = in.eb[1]; ebc[2] = in.eb[2];
 }
 
+// The interface shell of one reverse step written into a field buffer (E then H)
+// from the store: H at the low faces (blocks 0-5, interpolation qH) when do_h, E at
+// the high faces (blocks 6-11, interpolation qE) when do_e.  One thread t per face
+// cell and side; the first ax+ay+az threads take the low faces.
+__device__ inline int shell_threads(const Grid& g) {
+    return 2 * (g.my * g.mz + g.mx * g.mz + g.mx * g.my);
+}
+
+template <int DT>
+__device__ inline void shell_cell(const Grid& g, const ShellJob& j, int t) {
+    const int P = g.P;
+    const int ax = g.my * g.mz, ay = g.mx * g.mz, az = g.mx * g.my;   // face sizes (< 2^31: 24 N < 2^31)
+    const int face = ax + ay + az;
+    const bool high = t >= face;
+    if (high) t -= face;
+    if (t >= face || (high ? !j.do_e : !j.do_h)) return;
+    const int N = (int)g.N;
+    float* A = j.F + (high ? 0 : 3 * (long long)N);         // E for the high faces, H for the low ones
+    const Interp& q = high ? j.qE : j.qH;
+    const int b0 = high ? 6 : 0;
+    int x, y, z, c0, c1, blk, u;
+    if (t < ax) {
+        u = t; blk = b0; y = P + u % g.my; z = P + u / g.my; x = high ? g.nx - P : P - 1; c0 = 1; c1 = 2;
+    } else if (t < ax + ay) {
+        u = t - ax; blk = b0 + 2; x = P + u % g.mx; z = P + u / g.mx; y = high ? g.ny - P : P - 1; c0 = 2; c1 = 0;
+    } else {
+        u = t - ax - ay; blk = b0 + 4; x = P + u % g.mx; y = P + u / g.mx; z = high ? g.nz - P : P - 1;
+        c0 = 0; c1 = 1;
+    }
+    const int idx = x + g.nx * (y + g.ny * z);
+    A[c0 * N + idx] = shell_value_t<DT>(g, j.store, q, blk, u);
+    A[c1 * N + idx] = shell_value_t<DT>(g, j.store, q, blk + 1, u);
+}
+
+// the storage type is uniform over the launch: one branch per wave
+__device__ inline void shell_cell_any(const Grid& g, const ShellJob& j, int t) {
+    switch (g.dtype) {
+        case 0: shell_cell<0>(g, j, t); break;
+        case 1: shell_cell<1>(g, j, t); break;
+        case 2: shell_cell<2>(g, j, t); break;
+        case 3: shell_cell<3>(g, j, t); break;
+        case 4: shell_cell<4>(g, j, t); break;
+        case 5: shell_cell<5>(g, j, t); break;
+        case 6: shell_cell<6>(g, j, t); break;
+        case 7: shell_cell<7>(g, j, t); break;
+        case 8: shell_cell<8>(g, j, t); break;
+        default: shell_cell<9>(g, j, t); break;
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_inject_shell(Grid g, ShellJob j) {
+    shell_cell<DT>(g, j, (int)blockIdx.x * 256 + (int)threadIdx.x);
+}
+
 // One adjoint step: (Ebar, Hbar) in A0 and the auxiliaries in PML copy `pcopy` ->
 // A1 and copy 1 - pcopy.  Ebar already carries this step's loss seed (added by the
 // primal reversal).  Unrolled over the CZ planes and software-pipelined like the
-// forward sweep.
+// forward sweep.  Workgroups past the tile count write the shell `job`.
 #ifndef FDTD_ADJ_WAVES
 #define FDTD_ADJ_WAVES 1
 #endif
 template <int TY, int CZ>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_ADJ_WAVES))) void k_adj_step(
     Grid g, Tiling tl, const float* __restrict__ A0, float* __restrict__ A1, const float* __restrict__ eps,
-    float* __restrict__ psi, int pcopy) {
+    float* __restrict__ psi, int pcopy, ShellJob job) {
     __shared__ float sG[2][6][TY + 2][EXT];
     __shared__ float sGH[6][TY + 1][TX + 1];
     __shared__ CoefTile<TY, CZ> ct;
+    if ((int)blockIdx.x >= tl.count) {   // trailing workgroups: the next reverse step's interface shell
+        shell_cell_any(g, job, ((int)blockIdx.x - tl.count) * (TX * TY) + (int)(threadIdx.y * TX + threadIdx.x));
+        return;
+    }
     const int L = logical_tile(tl.count);
     const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
     FwdCtx<TY> c;
@@ -688,55 +760,34 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     }
 }
 
-// The interface shell of one reverse step written into a field buffer F (E then H)
-// from the store: H at the low faces (blocks 0-5, interpolation qH) when do_h, E at
-// the high faces (blocks 6-11, interpolation qE) when do_e.  One thread per face cell
-// and side; the first ax+ay+az threads take the low faces.
-template <int DT>
-__global__ __launch_bounds__(256) void k_inject_shell(Grid g, float* __restrict__ F, const void* __restrict__ store,
-                                                      Interp qE, Interp qH, int do_e, int do_h) {
-    const int P = g.P;
-    const int ax = g.my * g.mz, ay = g.mx * g.mz, az = g.mx * g.my;   // face sizes (< 2^31: 24 N < 2^31)
-    const int face = ax + ay + az;
-    int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
-    const bool high = t >= face;
-    if (high) t -= face;
-    if (t >= face || (high ? !do_e : !do_h)) return;
-    const int N = (int)g.N;
-    float* A = F + (high ? 0 : 3 * (long long)N);           // E for the high faces, H for the low ones
-    const Interp& q = high ? qE : qH;
-    const int b0 = high ? 6 : 0;
-    int x, y, z, c0, c1, blk, u;
-    if (t < ax) {
-        u = t; blk = b0; y = P + u % g.my; z = P + u / g.my; x = high ? g.nx - P : P - 1; c0 = 1; c1 = 2;
-    } else if (t < ax + ay) {
-        u = t - ax; blk = b0 + 2; x = P + u % g.mx; z = P + u / g.mx; y = high ? g.ny - P : P - 1; c0 = 2; c1 = 0;
-    } else {
-        u = t - ax - ay; blk = b0 + 4; x = P + u % g.mx; y = P + u / g.mx; z = high ? g.nz - P : P - 1;
-        c0 = 0; c1 = 1;
-    }
-    const int idx = x + g.nx * (y + g.ny * z);
-    A[c0 * N + idx] = shell_value_t<DT>(g, store, q, blk, u);
-    A[c1 * N + idx] = shell_value_t<DT>(g, store, q, blk + 1, u);
-}
-
 __global__ void k_scale_grad(double* g, long long n, const double* s) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) g[i] *= *s;
 }
 
+static long long shell_thread_count(const Grid& g) {
+    return 2 * ((long long)g.my * g.mz + (long long)g.mx * g.mz + (long long)g.mx * g.my);
+}
+
 template <int TY, int CZ>
 static void launch_adj_t(const Grid& g, const Tiling& t, const float* A0, float* A1, const float* eps, float* psi,
-                         int pcopy, hipStream_t s) {
-    launch_kernel(K_ADJ_STEP, k_adj_step<TY, CZ>, dim3(t.count), dim3(TX, TY), s, g, t, A0, A1, eps, psi, pcopy);
+                         int pcopy, const ShellJob* job, hipStream_t s) {
+    ShellJob j{};
+    long long extra = 0;
+    if (job && g.P > 0 && (job->do_e || job->do_h)) {
+        j = *job;
+        extra = (shell_thread_count(g) + TX * TY - 1) / (TX * TY);
+    }
+    launch_kernel(K_ADJ_STEP, k_adj_step<TY, CZ>, dim3((unsigned)(t.count + extra)), dim3(TX, TY), s, g, t, A0, A1,
+                  eps, psi, pcopy, j);
 }
 
 void launch_adj_step(const Grid& g, const Tiling& t, const float* A0, float* A1, const float* eps, float* psi,
-                     int pcopy, hipStream_t s) {
-    if (t.ty == 4 && t.cz == 4) launch_adj_t<4, 4>(g, t, A0, A1, eps, psi, pcopy, s);
-    else if (t.ty == 4) launch_adj_t<4, 8>(g, t, A0, A1, eps, psi, pcopy, s);
-    else if (t.cz == 4) launch_adj_t<8, 4>(g, t, A0, A1, eps, psi, pcopy, s);
-    else launch_adj_t<8, 8>(g, t, A0, A1, eps, psi, pcopy, s);
+                     int pcopy, const ShellJob* job, hipStream_t s) {
+    if (t.ty == 4 && t.cz == 4) launch_adj_t<4, 4>(g, t, A0, A1, eps, psi, pcopy, job, s);
+    else if (t.ty == 4) launch_adj_t<4, 8>(g, t, A0, A1, eps, psi, pcopy, job, s);
+    else if (t.cz == 4) launch_adj_t<8, 4>(g, t, A0, A1, eps, psi, pcopy, job, s);
+    else launch_adj_t<8, 8>(g, t, A0, A1, eps, psi, pcopy, job, s);
 }
 
 template <int TY, int CZ>
@@ -762,13 +813,11 @@ void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const i
     else launch_prim_rev_t<8, 8>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
 }
 
-void launch_inject_shell(const Grid& g, float* F, const void* store, Interp qE, Interp qH, int do_e, int do_h,
-                         hipStream_t s) {
-    if (g.P == 0 || (!do_e && !do_h)) return;
-    const long long n = 2 * ((long long)g.my * g.mz + (long long)g.mx * g.mz + (long long)g.mx * g.my);
+void launch_inject_shell(const Grid& g, const ShellJob& job, hipStream_t s) {
+    if (g.P == 0 || (!job.do_e && !job.do_h)) return;
+    const long long n = shell_thread_count(g);
     with_dtype(g.dtype, [&]<int DT>() {
-        launch_kernel(K_INJECT, k_inject_shell<DT>, dim3((unsigned)((n + 255) / 256)), dim3(256), s, g, F, store, qE,
-                      qH, do_e, do_h);
+        launch_kernel(K_INJECT, k_inject_shell<DT>, dim3((unsigned)((n + 255) / 256)), dim3(256), s, g, job);
     });
 }
 

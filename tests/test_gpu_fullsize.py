@@ -127,3 +127,33 @@ def test_c3p_compressed_gradient_vs_fp64_oracle(dtype, k, cos_min):
     c = metrics.cosine_similarity(g, exact)
     say("c3p %s k=%d vs FP64 oracle: cosine %.6f rel-L2 %.3e" % (dtype, k, c, metrics.rel_l2(g, exact)))
     assert c >= cos_min
+
+
+def test_c2pw_fp32_gradient_matches_fp64_oracle():
+    # plane-wave source (magnetic-current sheet) and flux objective at the benchmark size
+    require_gpu()
+    prob = w.c2pw(seed=0)
+    exact = _oracle_gradient(prob.name, 0)
+    g = gpu_run(prob, "fp32", 1, keep_fields=False)["grad"]
+    r, c = metrics.rel_l2(g, exact), metrics.cosine_similarity(g, exact)
+    say("c2pw fp32 k=1 vs FP64 oracle: rel-L2 %.3e cosine %.12f" % (r, c))
+    assert r <= 1e-5 and c >= 1 - 1e-9
+
+
+# At a 30-cell wavelength the step is 0.99/sqrt(3) of a cell, so a period spans about 52
+# steps: k = 16 keeps about 3.3 samples per period and the linear-in-time interpolation,
+# not the FP8 rounding, bounds the agreement (cosine 0.97 measured; 0.95 is the bar).
+@pytest.mark.parametrize("dtype,k,cos_min", [("fp32", 1, 1 - 1e-9), ("bf16", 4, 0.999),
+                                             ("fp8_e4m3_scaled", 16, 0.95)])
+def test_c5_crop_gradient_vs_fp64_oracle(dtype, k, cos_min):
+    # the slab-waveguide recipe of the 512x512x256 problem on a 128^3 crop, against the exact gradient
+    require_gpu()
+    prob = w.c5_crop(seed=0)
+    exact = _oracle_gradient(prob.name, 0)
+    g = gpu_run(prob, dtype, k, keep_fields=False)["grad"]
+    r, c = metrics.rel_l2(g, exact), metrics.cosine_similarity(g, exact)
+    say("c5 crop %s k=%d vs FP64 oracle: cosine %.9f rel-L2 %.3e" % (dtype, k, c, r))
+    assert c >= cos_min
+    if dtype == "fp32":
+        assert r <= 1e-5
+
