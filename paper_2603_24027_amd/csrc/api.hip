@@ -243,7 +243,8 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     pl->ws_mprofile = pl->ws_profile + align_up((uint64_t)pl->src_volume * 4, 256);
     pl->ws_partials = pl->ws_mprofile + align_up((uint64_t)pl->msrc_volume * 4, 256);
     pl->ws_staging = pl->ws_partials + align_up((uint64_t)p->steps * pl->per_step * 8, 256);
-    const uint64_t staging = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? align_up((uint64_t)vps * 4, 256) : 0;
+    const uint64_t staging =
+        cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? align_up((uint64_t)rec_quant_scratch_floats(g) * 4, 256) : 0;
     pl->ws_fields = pl->ws_staging + staging;
     // second primal and second adjoint field buffers (ping-pong)
     in.workspace_bytes = pl->ws_fields + 2 * in.fields_bytes;

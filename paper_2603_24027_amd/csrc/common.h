@@ -467,6 +467,8 @@ struct Tiling;
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
                      const float* eps, float wave, float mwave, double* partials,
                      void* store, float* staging, int slice, hipStream_t s);
+// scaled FP8 recorder: the staging values of one kept step, then the chunk maxima
+long long rec_quant_scratch_floats(const Grid& g);
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s);
 void launch_loss_final(const double* partials, int steps, int per_step, double* loss, double* series,
                        hipStream_t s);

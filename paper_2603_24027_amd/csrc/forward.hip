@@ -387,29 +387,48 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FW
     }
 }
 
-// FP8 recorder: one block per (face, component) block of a kept step.  absmax
-// (exact: max does not round), power-of-two scale, E4M3 codes.
-__global__ __launch_bounds__(256) void k_rec_quant(Grid g, const float* __restrict__ staging,
-                                                   void* __restrict__ store, int slice) {
-    const int b = blockIdx.x;
-    const long long off = block_offset(g, b), len = block_len(g, b);
-    const float* x = staging + off;
+// FP8 recorder of one kept step, in two launches over (chunk, block) grids so that
+// every compute unit takes part: the absmax of each chunk of each (face,
+// component) block of the FP32 staging copy (exact: max does not round), then
+// per block the power-of-two scale from the chunks' maxima and the E4M3 codes.
+// The chunk maxima sit after the staging values (REC_CHUNKS per block).
+constexpr int REC_CHUNKS = 64;
+
+__device__ inline void chunk_range(long long len, int chunks, int c, long long& lo, long long& hi) {
+    const long long per = (len + chunks - 1) / chunks;
+    lo = min(len, (long long)c * per);
+    hi = min(len, lo + per);
+}
+
+__global__ __launch_bounds__(256) void k_rec_absmax(Grid g, const float* __restrict__ staging,
+                                                    float* __restrict__ chunk_max, int chunks) {
+    const int c = blockIdx.x, b = blockIdx.y;
+    const long long off = block_offset(g, b);
+    long long lo, hi;
+    chunk_range(block_len(g, b), chunks, c, lo, hi);
     float m = 0.0f;
-    for (long long t = threadIdx.x; t < len; t += 256) m = fmaxf(m, fabsf(x[t]));
+    for (long long t = lo + threadIdx.x; t < hi; t += 256) m = fmaxf(m, fabsf(staging[off + t]));
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     __shared__ float red[4];
-    __shared__ float sc;
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float mm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-        sc = pow2f(fp8_scale_exp(mm));
-        ((float*)((char*)store + g.scale_off))[slice * 12 + b] = sc;
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) chunk_max[b * REC_CHUNKS + c] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void k_rec_encode(Grid g, const float* __restrict__ staging,
+                                                    const float* __restrict__ chunk_max, int chunks,
+                                                    void* __restrict__ store, int slice) {
+    const int c = blockIdx.x, b = blockIdx.y;
+    float mm = 0.0f;
+    for (int i = 0; i < chunks; ++i) mm = fmaxf(mm, chunk_max[b * REC_CHUNKS + i]);
+    const float sc = pow2f(fp8_scale_exp(mm));
+    if (c == 0 && threadIdx.x == 0) ((float*)((char*)store + g.scale_off))[slice * 12 + b] = sc;
     const float inv = 1.0f / sc;   // exact: sc is a power of two in the normal range
+    const long long off = block_offset(g, b);
+    long long lo, hi;
+    chunk_range(block_len(g, b), chunks, c, lo, hi);
     uint8_t* q = (uint8_t*)store + (long long)slice * g.slice_stride + off;
-    for (long long t = threadIdx.x; t < len; t += 256) q[t] = enc_e4m3(x[t] * inv);
+    for (long long t = lo + threadIdx.x; t < hi; t += 256) q[t] = enc_e4m3(staging[off + t] * inv);
 }
 
 // Fixed-order FP64 reduction of the detector partials: per-step terms, then their sum.
@@ -472,8 +491,18 @@ void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1,
         launch_fwd_step_m<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
 }
 
+long long rec_quant_scratch_floats(const Grid& g) {
+    return ((g.vps + 63) / 64) * 64 + 12 * REC_CHUNKS;
+}
+
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s) {
-    launch_kernel(K_REC_QUANT, k_rec_quant, dim3(12), dim3(256), s, g, staging, store, slice);
+    long long longest = 0;
+    for (int b = 0; b < 12; ++b) longest = std::max(longest, (long long)block_len(g, b));
+    const int chunks = (int)std::min<long long>(REC_CHUNKS, std::max<long long>(1, (longest + 2047) / 2048));
+    float* chunk_max = const_cast<float*>(staging) + ((g.vps + 63) / 64) * 64;
+    launch_kernel(K_REC_QUANT, k_rec_absmax, dim3(chunks, 12), dim3(256), s, g, staging, chunk_max, chunks);
+    launch_kernel(K_REC_QUANT, k_rec_encode, dim3(chunks, 12), dim3(256), s, g, staging, chunk_max, chunks, store,
+                  slice);
 }
 
 void launch_loss_final(const double* partials, int steps, int per_step, double* loss, double* series,
