@@ -658,12 +658,13 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     else if (row == 1) { c.rlx = lane + 1; c.rly = TY + 1; c.ring = make_col(g, c.i0 + lane, c.j0 + TY); }
     else if (row == 2 && lane < TY + 2) { c.rlx = 0; c.rly = lane; c.ring = make_col(g, c.i0 - 1, c.j0 - 1 + lane); }
     else if (row == 3 && lane < TY + 2) { c.rlx = EXT - 1; c.rly = lane; c.ring = make_col(g, c.i0 + TX, c.j0 - 1 + lane); }
-    // extra E^n position: the column x = i0+TX (tid <= TY) or the row y = j0+TY
+    // extra E^n positions: the row y = j0+TY (wave 2) and the column x = i0+TX (wave 3),
+    // away from the ring rows of waves 0 and 1
     c.pex = c.pey = -1;
     c.xcol.xy = -1;
     c.xcol.x = c.xcol.y = -1;
-    if (tid < TY + 1) { c.pex = TX; c.pey = tid; }
-    else if (tid < TY + 1 + TX) { c.pex = tid - TY - 1; c.pey = TY; }
+    if (row == 2) { c.pex = lane; c.pey = TY; }
+    else if (row == 3 && lane < TY + 1) { c.pex = TX; c.pey = lane; }
     if (c.pex >= 0) c.xcol = make_col(g, c.i0 + c.pex, c.j0 + c.pey);
     RevLanes Ln;
     // without wrap-around, idle lanes (outside the box) are never a neighbour of a box cell
