@@ -396,6 +396,9 @@ int run_sequence(uint64_t key, hipStream_t s, Enqueue&& enqueue, const char* wha
 uint64_t call_key(const Plan& pl, int dir, const fdtd_store_cfg_t* cfg, std::initializer_list<const void*> ptrs) {
     uint64_t h = fnv1a(pl.hash, &dir, sizeof dir);
     h = fnv1a(h, cfg, sizeof *cfg);
+    // the tile shapes (they can be changed between calls through the environment)
+    const int tiles[6] = {pl.fwd.ty, pl.fwd.cz, pl.adj.ty, pl.adj.cz, pl.rev.ty, pl.rev.cz};
+    h = fnv1a(h, tiles, sizeof tiles);
     for (const void* p : ptrs) h = fnv1a(h, &p, sizeof p);
     return h;
 }

@@ -330,3 +330,34 @@ def test_tfsf_compressed_against_oracle_compressed():
     cos = metrics.cosine_similarity(out["grad"], g)
     say("  bf16 k=3 plane wave: cosine vs oracle-compressed %.8f" % cos)
     assert cos >= 0.9999
+
+
+# --------------------------------------------------------------------------- tile shapes
+
+TILES = {
+    "fwd8x4": {"FDTD_TILE_Y": "8", "FDTD_TILE_Z": "4"},
+    "fwd8x8": {"FDTD_TILE_Y": "8", "FDTD_TILE_Z": "8"},
+    "adj4x8": {"FDTD_ADJ_TILE_Y": "4", "FDTD_ADJ_TILE_Z": "8"},   # the large-grid default
+    "adj4x4_rev8x8": {"FDTD_ADJ_TILE_Y": "4", "FDTD_ADJ_TILE_Z": "4", "FDTD_REV_TILE_Y": "8",
+                      "FDTD_REV_TILE_Z": "8"},
+    "adj8x4_rev4x8_fwd4x4": {"FDTD_ADJ_TILE_Y": "8", "FDTD_ADJ_TILE_Z": "4", "FDTD_REV_TILE_Y": "4",
+                             "FDTD_REV_TILE_Z": "8", "FDTD_TILE_Y": "4", "FDTD_TILE_Z": "4"},
+}
+
+
+@pytest.mark.parametrize("tiles", list(TILES))
+@pytest.mark.parametrize("case", ["ragged", "kappa"])
+def test_every_tile_shape_against_oracle(tiles, case, monkeypatch):
+    # every instantiated sweep shape, including the ones only large grids select by default
+    require_gpu()
+    for name, value in TILES[tiles].items():
+        monkeypatch.setenv(name, value)
+    prob = CASES[case]()
+    say("tile shapes", tiles, case)
+    out = gpu_run(prob, "fp16", 3)
+    L, g = adjoint.grad_time_reversal(prob, "fp16", 3, match_fp32=True)
+    assert abs(out["loss"] - L) <= 1e-5 * abs(L)
+    r = rel(out["grad"], g)
+    cos = metrics.cosine_similarity(out["grad"], g)
+    say("  rel-L2 %.3e cosine %.12f" % (r, cos))
+    assert cos >= 0.9999 and r <= 1e-2
