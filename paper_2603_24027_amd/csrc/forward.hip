@@ -239,11 +239,14 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
 // The z-march over CZ planes is unrolled and software-pipelined: the loads of plane
 // k+1 are issued before the stores of plane k into the other of two register sets,
 // so no wait for them also waits for those stores (loads and stores retire in order).
+// With a magnetic-current sheet the sweep asks for 4 waves per SIMD: left free it
+// takes 132 vector registers (3 waves, 24 % slower); held to 128 it spills only
+// scalars, into vector-register lanes.
 #ifndef FDTD_FWD_WAVES
 #define FDTD_FWD_WAVES 1
 #endif
 template <int TY, int REC, int CZ, bool MS>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_FWD_WAVES))) void k_fwd_step(
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MS ? 4 : FDTD_FWD_WAVES))) void k_fwd_step(
     Grid g, Tiling tl, const float* __restrict__ F0, float* __restrict__ F1, float* __restrict__ psi, int hcopy,
     const float* __restrict__ eps, float wave, float mwave, double* __restrict__ partials,
     void* __restrict__ store, float* __restrict__ staging, int slice) {
