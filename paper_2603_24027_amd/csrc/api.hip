@@ -298,7 +298,7 @@ int check_hip(const char* what) {
 }
 
 // ---- per-kernel timing ------------------------------------------------------
-const char* kKindNames[K_NUM_KINDS] = {"fill", "fwd_step", "rec_quant", "loss_final", "inject_h",
+const char* kKindNames[K_NUM_KINDS] = {"fill", "fwd_step", "rec_quant", "loss_final", "inject_shell",
                                        "prim_rev", "adj_step", "scale_grad", "codec"};
 constexpr size_t kMaxTimedLaunches = 1 << 16;
 

@@ -613,7 +613,8 @@ __device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const R
 // One reverse primal step over the box: (E^{n+1}, H^{n+1/2}) in F0 -> (E^n, H^{n-1/2})
 // in F1 on the interior, with the gradient and the loss seed.  The interface shell of
 // F1 (E^n on the high faces, H^{n-1/2} on the low faces) is written beforehand from the
-// store (k_inject_shell); the sweep reads the E part of it.
+// store (by the previous adjoint launch, or k_inject_shell on the first reverse step);
+// the sweep reads the E part of it.
 #ifndef FDTD_REV_WAVES
 #define FDTD_REV_WAVES 1
 #endif
