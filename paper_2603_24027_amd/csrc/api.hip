@@ -215,10 +215,24 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     Tiling& r = pl->rev;
     r = t;
     r.ty = env_int("FDTD_REV_TILE_Y", 4) == 8 ? 8 : 4;
-    r.cz = env_int("FDTD_REV_TILE_Z", 4) == 8 ? 8 : 4;
     pl->rev_x0 = pl->box_o[0] & ~31;
     r.ntx = (pl->box_o[0] + pl->box_n[0] - pl->rev_x0 + TX - 1) / TX;
     r.nty = (pl->box_n[1] + r.ty - 1) / r.ty;
+    {
+        // Depth of the reversal's tiles: among 4, 5 and 6 planes, the one whose tile count
+        // fills most of one round (five 4-wave workgroups on each of 256 compute units)
+        // when some depth fits in a round, else 6 (the least re-read z halo).  Measured at
+        // 128^3 (one round at depth 5: 22.0 -> 20.6 us) and 256x256x128 (depth 6).
+        const long long slots = 5 * 256, cols = (long long)r.ntx * r.nty;
+        int pick = 6;
+        long long best = 0;
+        for (int cz = 4; cz <= 6; ++cz) {
+            const long long n = cols * ((pl->box_n[2] + cz - 1) / cz);
+            if (n <= slots && n > best) { best = n; pick = cz; }
+        }
+        const int cz = env_int("FDTD_REV_TILE_Z", r.ty == 4 ? pick : 4);
+        r.cz = (cz == 8 || (r.ty == 4 && (cz == 5 || cz == 6))) ? cz : 4;
+    }
     r.ntz = (pl->box_n[2] + r.cz - 1) / r.cz;
     r.count = r.ntx * r.nty * r.ntz;
     pl->psi_floats = (uint64_t)g.psi_total;

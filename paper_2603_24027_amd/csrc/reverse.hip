@@ -810,6 +810,8 @@ void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const i
     for (int d = 0; d < 3; ++d) { b.o[d] = box_o[d]; b.n[d] = box_n[d]; }
     b.tx0 = tile_x0;
     if (t.ty == 4 && t.cz == 4) launch_prim_rev_t<4, 4>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
+    else if (t.ty == 4 && t.cz == 5) launch_prim_rev_t<4, 5>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
+    else if (t.ty == 4 && t.cz == 6) launch_prim_rev_t<4, 6>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
     else if (t.ty == 4) launch_prim_rev_t<4, 8>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
     else if (t.cz == 4) launch_prim_rev_t<8, 4>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
     else launch_prim_rev_t<8, 8>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);

@@ -340,6 +340,8 @@ TILES = {
     "adj4x8": {"FDTD_ADJ_TILE_Y": "4", "FDTD_ADJ_TILE_Z": "8"},   # the large-grid default
     "adj4x4_rev8x8": {"FDTD_ADJ_TILE_Y": "4", "FDTD_ADJ_TILE_Z": "4", "FDTD_REV_TILE_Y": "8",
                       "FDTD_REV_TILE_Z": "8"},
+    "rev4x5": {"FDTD_REV_TILE_Z": "5"},
+    "rev4x6": {"FDTD_REV_TILE_Z": "6"},
     "adj8x4_rev4x8_fwd4x4": {"FDTD_ADJ_TILE_Y": "8", "FDTD_ADJ_TILE_Z": "4", "FDTD_REV_TILE_Y": "4",
                              "FDTD_REV_TILE_Z": "8", "FDTD_TILE_Y": "4", "FDTD_TILE_Z": "4"},
 }
