@@ -225,29 +225,6 @@ __device__ inline float dec_unscaled(int dtype, uint8_t c) {
     }
 }
 
-// Decode one stored value (the scaled FP8 type needs its block scale).
-__device__ inline float load_code(const void* store, long long byte_slice, long long off, int dtype, float scale) {
-    const char* base = (const char*)store + byte_slice;
-    switch (dtype) {
-        case 0: return ((const float*)base)[off];
-        case 1: return dec_fp16(((const uint16_t*)base)[off]);
-        case 2: return dec_bf16(((const uint16_t*)base)[off]);
-        case 3: return dec_e4m3(((const uint8_t*)base)[off]) * scale;
-        default: return dec_unscaled(dtype, ((const uint8_t*)base)[off]);
-    }
-}
-
-__device__ inline void store_code(void* store, long long byte_slice, long long off, int dtype, float v) {
-    char* base = (char*)store + byte_slice;
-    switch (dtype) {
-        case 0: ((float*)base)[off] = v; break;
-        case 1: ((uint16_t*)base)[off] = enc_fp16(v); break;
-        case 2: ((uint16_t*)base)[off] = enc_bf16(v); break;
-        case 3: break;   // the scaled FP8 type goes through the staging buffer and the quantiser kernel
-        default: ((uint8_t*)base)[off] = enc_unscaled(dtype, v); break;
-    }
-}
-
 // ----------------------------------------------------------------------------
 // Interface shell geometry: 12 blocks per kept step, in this order
 //   0,1  x-low  (Hy, Hz) at i = P-1      [k][j]
@@ -291,18 +268,6 @@ struct ShellJob {
     int do_e, do_h;
 };
 
-__device__ inline float shell_value(const Grid& g, const void* store, const Interp& q, int b, long long off) {
-    long long o = block_offset(g, b) + off;
-    const float* scales = (const float*)((const char*)store + g.scale_off);
-    float s1 = g.dtype == 3 ? scales[q.j1 * 12 + b] : 1.0f;
-    float v = q.w1 * load_code(store, q.j1 * g.slice_stride, o, g.dtype, s1);
-    if (q.j0 >= 0) {
-        float s0 = g.dtype == 3 ? scales[q.j0 * 12 + b] : 1.0f;
-        v += q.w0 * load_code(store, q.j0 * g.slice_stride, o, g.dtype, s0);
-    }
-    return v;
-}
-
 // Compile-time storage type versions (the sweeps are instantiated per type so
 // that no conversion code other than the one in use enters a kernel).
 template <int DT>
@@ -320,27 +285,10 @@ __device__ inline float load_code_t(const void* store, long long byte_slice, lon
     else return dec_f8<4, 3, 7, 1>(((const uint8_t*)base)[off]);
 }
 
-// Record one value of a kept step: the scaled FP8 type goes to the FP32 staging
-// buffer (quantised per block afterwards), every other type straight to the store.
-template <int DT>
-__device__ inline void record_t(void* store, float* staging, long long byte_slice, long long off, float v) {
-    char* base = (char*)store + byte_slice;
-    if constexpr (DT == 0) ((float*)base)[off] = v;
-    else if constexpr (DT == 1) ((uint16_t*)base)[off] = enc_fp16(v);
-    else if constexpr (DT == 2) ((uint16_t*)base)[off] = enc_bf16(v);
-    else if constexpr (DT == 3) staging[off] = v;
-    else if constexpr (DT == 4) ((uint8_t*)base)[off] = enc_f8<4, 3, 11, 2>(v);
-    else if constexpr (DT == 5) ((uint8_t*)base)[off] = enc_f8<5, 2, 16, 2>(v);
-    else if constexpr (DT == 6) ((uint8_t*)base)[off] = enc_f8<4, 3, 8, 2>(v);
-    else if constexpr (DT == 7) ((uint8_t*)base)[off] = enc_f8<4, 3, 7, 0>(v);
-    else if constexpr (DT == 8) ((uint8_t*)base)[off] = enc_f8<3, 4, 3, 0>(v);
-    else ((uint8_t*)base)[off] = enc_f8<4, 3, 7, 1>(v);
-}
-
 // Record one value of a kept step through a range-checked buffer store (dropped
 // when `on` is false): `r` covers the kept step's slice of the store, or for the
-// scaled FP8 type the FP32 staging buffer; `elem` is the element index within it
-// (block offset + position).
+// scaled FP8 type the FP32 staging buffer (quantised per block afterwards);
+// `elem` is the element index within it (block offset + position).
 template <int DT>
 __device__ inline void record_b(__amdgpu_buffer_rsrc_t r, uint32_t elem, bool on, float v) {
     const uint32_t oob = 0x80000000u;

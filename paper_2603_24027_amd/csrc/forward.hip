@@ -270,7 +270,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MS ? 4 
     c.N = (int)g.N;
     c.P = g.P;
     c.plane = g.nx * g.ny;
-    const int N = c.N, P = c.P, plane = c.plane, lane = c.lane, row = c.row;
+    const int N = c.N, plane = c.plane, lane = c.lane, row = c.row;
     const uint32_t nb = (uint32_t)N << 2;
     FwdBufs b;
     const uint32_t fbytes = (uint32_t)(6 * N) * 4u, psib = (uint32_t)g.psi_total * 4u;

@@ -242,11 +242,8 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
 // The interface shell of one reverse step written into a field buffer (E then H)
 // from the store: H at the low faces (blocks 0-5, interpolation qH) when do_h, E at
 // the high faces (blocks 6-11, interpolation qE) when do_e.  One thread t per face
-// cell and side; the first ax+ay+az threads take the low faces.
-__device__ inline int shell_threads(const Grid& g) {
-    return 2 * (g.my * g.mz + g.mx * g.mz + g.mx * g.my);
-}
-
+// cell and side (2 (my mz + mx mz + mx my) in all); the first ax+ay+az threads take
+// the low faces.
 template <int DT>
 __device__ inline void shell_cell(const Grid& g, const ShellJob& j, int t) {
     const int P = g.P;
@@ -633,7 +630,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     const int k1 = min(k0 + CZ, bx.o[2] + bx.n[2]);
     c.lane = threadIdx.x;
     c.row = threadIdx.y;
-    const int lane = c.lane, row = c.row, tid = row * TX + lane;
+    const int lane = c.lane, row = c.row;
     c.x = c.i0 + lane;
     c.y = c.j0 + row;
     c.live = c.x >= bx.o[0] && c.x < bx.o[0] + bx.n[0] && c.y < bx.o[1] + bx.n[1];
