@@ -243,8 +243,10 @@ FDTD_API int fdtd_timing_enable(int32_t enable);
  * problem, store configuration, buffer pointers and device equal those of an
  * earlier call replays that call's kernel sequence as one HIP graph (captured
  * once, up to 16 kept) instead of enqueuing T launches from the host; the
- * kernels and their results are the same.  fdtd_set_graphs(0) enqueues every
- * launch directly.  Per-kernel timing always enqueues directly.
+ * kernels and their results are the same.  A 17th distinct call evicts the
+ * oldest graph, and that call first waits (on the host) for the evicted graph's
+ * last launch to finish.  fdtd_set_graphs(0) enqueues every launch directly.
+ * Per-kernel timing always enqueues directly.
  */
 FDTD_API int fdtd_set_graphs(int32_t enable);
 FDTD_API int fdtd_timing_read(fdtd_kernel_time_t* out, int32_t max_kinds);

@@ -329,11 +329,16 @@ struct Timing {
 // replays that call's launch sequence as one graph: the T-step loop is
 // captured once (on an internal stream) and then launched on the caller's
 // stream.  Per-kernel timing bypasses graphs.
+struct GraphEntry {
+    uint64_t key;
+    hipGraphExec_t exec;
+    hipEvent_t done;     // recorded after every launch: eviction waits for the last one
+};
 struct GraphCache {
     std::mutex mu;
     bool enabled = true;
-    std::vector<std::pair<uint64_t, hipGraphExec_t>> entries;   // most recent last
-    hipStream_t capture[64] = {};                                // per device
+    std::vector<GraphEntry> entries;   // most recent last
+    hipStream_t capture[64] = {};      // per device
 } g_graphs;
 constexpr size_t kMaxGraphs = 16;
 
@@ -375,9 +380,9 @@ int run_sequence(uint64_t key, hipStream_t s, Enqueue&& enqueue, const char* wha
     }
     key = fnv1a(key, &dev, sizeof dev);
     std::lock_guard<std::mutex> lk(g_graphs.mu);
-    for (size_t i = 0; i < g_graphs.entries.size(); ++i) {
-        if (g_graphs.entries[i].first == key) {
-            if (hipGraphLaunch(g_graphs.entries[i].second, s) != hipSuccess)
+    for (GraphEntry& e : g_graphs.entries) {
+        if (e.key == key) {
+            if (hipGraphLaunch(e.exec, s) != hipSuccess || hipEventRecord(e.done, s) != hipSuccess)
                 return fail(FDTD_EHIP, "%s: graph launch failed", what);
             return check_hip(what);
         }
@@ -398,12 +403,22 @@ int run_sequence(uint64_t key, hipStream_t s, Enqueue&& enqueue, const char* wha
     const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
     if (ie != hipSuccess) return fail(FDTD_EHIP, "%s: graph instantiation failed: %s", what, hipGetErrorString(ie));
+    hipEvent_t done = nullptr;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+        hipGraphExecDestroy(exec);
+        return fail(FDTD_EHIP, "%s: event creation failed", what);
+    }
     if (g_graphs.entries.size() >= kMaxGraphs) {
-        hipGraphExecDestroy(g_graphs.entries.front().second);
+        // the oldest graph may still run on some stream: wait for its last launch
+        GraphEntry& old = g_graphs.entries.front();
+        hipEventSynchronize(old.done);
+        hipGraphExecDestroy(old.exec);
+        hipEventDestroy(old.done);
         g_graphs.entries.erase(g_graphs.entries.begin());
     }
-    g_graphs.entries.emplace_back(key, exec);
-    if (hipGraphLaunch(exec, s) != hipSuccess) return fail(FDTD_EHIP, "%s: graph launch failed", what);
+    g_graphs.entries.push_back(GraphEntry{key, exec, done});
+    if (hipGraphLaunch(exec, s) != hipSuccess || hipEventRecord(done, s) != hipSuccess)
+        return fail(FDTD_EHIP, "%s: graph launch failed", what);
     return check_hip(what);
 }
 

@@ -363,3 +363,26 @@ def test_every_tile_shape_against_oracle(tiles, case, monkeypatch):
     cos = metrics.cosine_similarity(out["grad"], g)
     say("  rel-L2 %.3e cosine %.12f" % (r, cos))
     assert cos >= 0.9999 and r <= 1e-2
+
+
+def test_graph_cache_eviction_with_calls_in_flight():
+    """More distinct calls than the graph cache keeps, enqueued without synchronising:
+    evicting a graph waits for its last launch, and every result equals the eager one."""
+    require_gpu()
+    prob = w.tiny(steps=40)
+    pk.set_graphs(False)
+    try:
+        ref = gpu_run(prob, "fp16", 2, keep_fields=False)
+    finally:
+        pk.set_graphs(True)
+    eps = torch.from_numpy(prob.eps).cuda()
+    objs, outs = [], []
+    for i in range(12):                       # 24 distinct calls (forward and backward each)
+        g = pk.Gradient(prob, "fp16", 2)
+        loss = g.forward(eps)
+        outs.append((loss, g.backward()))
+        objs.append(g)
+    torch.cuda.synchronize()
+    for loss, grad in outs:
+        assert float(loss.item()) == ref["loss"]
+        assert np.array_equal(grad.cpu().numpy(), ref["grad"])
