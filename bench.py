@@ -221,6 +221,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compressed", action="store_true")
+    ap.add_argument("--no-crop", action="store_true", help="skip the 128^3-crop gradient errors (c5)")
     ap.add_argument("--cpu-sample-steps", type=int, default=60)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for counter scaling) and exit")
@@ -402,7 +403,7 @@ def main():
             errs["%s_k%d" % (c_obj.dtype, c_obj.k)] = c_obj.buf.grad.cpu().numpy()
         out["grad_err_vs_fp64_oracle"] = {
             name: {"rel_l2": rel_l2(g, exact), "cosine": cosine(g, exact)} for name, g in errs.items()}
-    if args.workload in CROPS:
+    if args.workload in CROPS and not args.no_crop:
         # gradient error of every storage setting on the 128^3 crop of this workload's recipe
         cprob = w.make(CROPS[args.workload], seed=0)
         cexact = oracle_gradient(cprob.name, 0)
