@@ -188,6 +188,11 @@ FDTD_API int store_config(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cf
  *   rec         host: out, token for fdtd_backward
  *   stream      hipStream_t (NULL = default stream)
  * Asynchronous: returns after enqueueing; nothing is synchronised.
+ * Tile shapes are chosen from the grid; the environment variables
+ * FDTD_TILE_Y/Z (forward), FDTD_ADJ_TILE_Y/Z and FDTD_REV_TILE_Y/Z (the two
+ * reverse sweeps) override them for tuning (Y: 4 or 8 rows; Z: planes per
+ * tile, 4 or 8, and 5 or 6 for the reversal with 4 rows); results do not
+ * depend on them beyond FP32 rounding order.
  */
 FDTD_API int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg,
                  const float* eps, float* fields, float* psi, void* store, void* workspace,
