@@ -24,8 +24,8 @@
  *
  * Ownership: every pointer is owned by the caller.  The library never
  * allocates, frees or synchronises device memory; it only launches kernels
- * and asynchronous copies on the caller's HIP stream.  Host pointers
- * (source signal and profile) are read before the call returns.
+ * on the caller's HIP stream.  Host pointers (source signal and profiles)
+ * are read before the call returns.
  *
  * Errors: every entry point returns 0 on success or a negative FDTD_E* code;
  * fdtd_last_error() gives a message for the calling thread.  All argument
@@ -161,6 +161,21 @@ typedef struct {
     uint64_t design_cells;      /* cells of the design box (length of the gradient)      */
 } fdtd_store_info_t;
 
+/* Layout of the store buffer (read it only for inspection; the backward call
+ * decodes it itself).  Kept step j (j = 0 .. slices-1 holds time step T-1-j*k)
+ * starts at byte j * S, S = values_per_slice * storage bytes rounded up to a
+ * multiple of 256.  Within a kept step, 12 (face, component) blocks follow each
+ * other, each over the interior extent of the face's two other axes:
+ *    0, 1  x-low face,  index P-1:    Hy, Hz   as [z][y]   (my * mz values each)
+ *    2, 3  y-low face,  index P-1:    Hz, Hx   as [z][x]   (mx * mz)
+ *    4, 5  z-low face,  index P-1:    Hx, Hy   as [y][x]   (mx * my)
+ *    6, 7  x-high face, index nx-P:   Ey, Ez   as [z][y]
+ *    8, 9  y-high face, index ny-P:   Ez, Ex   as [z][x]
+ *   10, 11 z-high face, index nz-P:   Ex, Ey   as [y][x]
+ * (H^{n+1/2} on the low faces and E^n on the high faces of time step n.)  For
+ * FDTD_STORE_FP8_E4M3_SCALED the float scales follow at byte slices * S, 12
+ * per kept step in block order. */
+
 /* Host-side token tying a backward call to the forward call that recorded the store. */
 typedef struct {
     uint64_t problem_hash;
@@ -181,13 +196,17 @@ FDTD_API int store_config(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cf
  *   fields      device, fields_bytes: out, E^T then H^{T-1/2} (zeroed by the call first)
  *   psi         device, psi_bytes: PML auxiliaries (scratch, zeroed by the call)
  *   store       device, store_bytes: out, recorded interface fields
- *   workspace   device, workspace_bytes: scratch; must stay untouched until the
- *               matching fdtd_backward (it keeps the coefficient tables)
+ *   workspace   device, workspace_bytes: scratch (the call writes the CPML
+ *               coefficient table and source profiles into it itself; nothing in it
+ *               is needed after the call's kernels end)
  *   loss        device, 1 double: out, L
  *   loss_series device, T doubles or NULL: out, per-step terms of L
  *   rec         host: out, token for fdtd_backward
  *   stream      hipStream_t (NULL = default stream)
- * Asynchronous: returns after enqueueing; nothing is synchronised.
+ * Asynchronous: returns after enqueueing; nothing is synchronised.  The host
+ * arrays of the problem (source signal and profiles) are read before the call
+ * returns: the few values they contribute travel as kernel arguments, so no
+ * host memory is read by the device afterwards.
  * Tile shapes are chosen from the grid; the environment variables
  * FDTD_TILE_Y/Z (forward), FDTD_ADJ_TILE_Y/Z and FDTD_REV_TILE_Y/Z (the two
  * reverse sweeps) override them for tuning (Y: 4 or 8 rows; Z: planes per
@@ -203,7 +222,7 @@ FDTD_API int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cf
  * one extra simulation; Section 2: interface fields injected as sources).
  *   fields      device, in: the final state left by fdtd_forward; destroyed
  *   store       device, in: the record written by fdtd_forward
- *   workspace   device: the same buffer that fdtd_forward used
+ *   workspace   device, workspace_bytes: scratch (need not be the forward's buffer)
  *   adj_fields  device, fields_bytes: scratch for the adjoint fields
  *   adj_psi     device, adj_psi_bytes: scratch for the adjoint PML auxiliaries
  *   grad_scale  device, 1 double or NULL: the gradient is multiplied by it

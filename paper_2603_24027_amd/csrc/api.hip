@@ -66,7 +66,7 @@ struct Plan {
     int64_t src_volume = 0;
     int64_t msrc_volume = 0;       // 0: no magnetic current
     uint64_t ws_mprofile = 0;
-    std::vector<float> coef;   // 12 P floats
+    float coef[12 * FDTD_MAX_PML];   // 12 P used
     uint64_t hash = 0;
 };
 
@@ -79,9 +79,9 @@ bool box_inside_interior(const int32_t lo[3], const int32_t hi[3], const int n[3
 // CPML tables indexed by the slab coordinate i' in [0, 2P).  Depth from the
 // interior boundary: E nodes (x = i) and H nodes (x = i + 1/2); the low slab
 // has i' = i, the high slab i' = i - (n - 2P), so the depth depends on i' only.
-void cpml_tables(const fdtd_problem_t* p, double dt, std::vector<float>& coef) {
+void cpml_tables(const fdtd_problem_t* p, double dt, float* coef) {
     const int P = p->pml;
-    coef.assign(12 * (size_t)P, 0.0f);
+    std::fill(coef, coef + 12 * (size_t)P, 0.0f);
     const double m = p->pml_order;
     const double sig_max = p->pml_sigma_scale * 0.8 * (m + 1.0);
     for (int node = 0; node < 2; ++node) {
@@ -96,7 +96,7 @@ void cpml_tables(const fdtd_problem_t* p, double dt, std::vector<float>& coef) {
             const double alpha = p->pml_alpha_max * (1.0 - rho);
             const double b = std::exp(-(sigma / kappa + alpha) * dt);
             const double a = sigma > 0.0 ? sigma * (b - 1.0) / (sigma * kappa + kappa * kappa * alpha) : 0.0;
-            float* base = coef.data() + (size_t)node * 6 * P;
+            float* base = coef + (size_t)node * 6 * P;
             base[s] = (float)b;
             base[2 * P + s] = (float)a;
             base[4 * P + s] = (float)(1.0 / kappa);
@@ -288,6 +288,16 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     return FDTD_OK;
 }
 
+// The CPML coefficient table and the source profiles into the workspace, written by
+// kernel launches that carry the values (so a captured graph holds them, and the
+// call reads no host memory after it returns).  Both directions write them, so a
+// backward call needs nothing that its forward left in the workspace.
+void put_tables(const Plan& pl, const fdtd_problem_t* prob, char* ws, hipStream_t q) {
+    launch_put((float*)(ws + pl.ws_coef), pl.coef, 12LL * pl.g.P, q);
+    launch_put((float*)(ws + pl.ws_profile), prob->src_profile, pl.src_volume, q);
+    if (pl.msrc_volume > 0) launch_put((float*)(ws + pl.ws_mprofile), prob->msrc_profile, pl.msrc_volume, q);
+}
+
 Interp interp_for(int n, int T, int k) {
     Interp q;
     if ((T - 1 - n) % k == 0) {
@@ -313,7 +323,7 @@ int check_hip(const char* what) {
 
 // ---- per-kernel timing ------------------------------------------------------
 const char* kKindNames[K_NUM_KINDS] = {"fill", "fwd_step", "rec_quant", "loss_final", "inject_shell",
-                                       "prim_rev", "adj_step", "scale_grad", "codec"};
+                                       "prim_rev", "adj_step", "scale_grad", "codec", "put"};
 constexpr size_t kMaxTimedLaunches = 1 << 16;
 
 struct Timing {
@@ -366,11 +376,11 @@ bool timing_acquire(int kind, hipEvent_t* start, hipEvent_t* stop) {
 namespace {
 
 template <class Enqueue>
-int run_sequence(uint64_t key, hipStream_t s, Enqueue&& enqueue, const char* what) {
+int run_sequence(uint64_t key, hipStream_t s, Enqueue&& enqueue, const char* what, bool allow_graph = true) {
     bool use_graph;
     {
         std::lock_guard<std::mutex> lk(g_graphs.mu);
-        use_graph = g_graphs.enabled && !g_timing.enabled;
+        use_graph = allow_graph && g_graphs.enabled && !g_timing.enabled;
     }
     int dev = 0;
     if (use_graph && (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)) use_graph = false;
@@ -432,6 +442,51 @@ uint64_t call_key(const Plan& pl, int dir, const fdtd_store_cfg_t* cfg, std::ini
     return h;
 }
 
+// The forward time loop on the workspace `ws`.
+int forward_with(const Plan& pl, const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const float* eps,
+                 float* fields, float* psi, void* store, char* ws, double* loss, double* loss_series,
+                 fdtd_record_t* rec, hipStream_t s, bool allow_graph, const char* what) {
+    Grid g = pl.g;
+    g.coef = (const float*)(ws + pl.ws_coef);
+    g.src_profile = (const float*)(ws + pl.ws_profile);
+    g.msrc_profile = (const float*)(ws + pl.ws_mprofile);
+    double* partials = (double*)(ws + pl.ws_partials);
+    float* staging = (float*)(ws + pl.ws_staging);
+
+    const int64_t N = g.N;
+    const int T = prob->steps, k = cfg->k;
+    // ping-pong field buffers; the parity of T picks the start so that the
+    // final state lands in the caller's buffer
+    float* F[2] = {fields, (float*)(ws + pl.ws_fields)};
+    const int start = T & 1;
+    const bool fp8 = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED && g.vps > 0;
+    const float* wave = prob->src_wave;
+    auto mwave = [&](int n) { return pl.msrc_volume > 0 ? prob->msrc_wave[n] : 0.0f; };
+    auto enqueue = [&](hipStream_t q) {
+        put_tables(pl, prob, ws, q);
+        launch_fill(F[start], 6 * N, 0.0f, q);
+        launch_fill(psi, 2 * (long long)pl.psi_floats, 0.0f, q);
+        for (int n = 0; n < T; ++n) {
+            const int slice = ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1;
+            const float* in = F[(start + n) & 1];
+            float* out = F[(start + n + 1) & 1];
+            launch_fwd_step(g, pl.fwd, in, out, psi, n & 1, eps, wave[n], mwave(n),
+                            partials + (int64_t)n * pl.per_step, store, staging, slice, q);
+            if (slice >= 0 && fp8) launch_rec_quant(g, staging, store, slice, q);
+        }
+        launch_loss_final(partials, T, pl.per_step, loss, loss_series, q);
+    };
+    const int rc = run_sequence(call_key(pl, 0, cfg, {eps, fields, psi, store, ws, loss, loss_series}), s, enqueue,
+                                what, allow_graph);
+    if (rc) return rc;
+    rec->problem_hash = pl.hash;
+    rec->dtype = cfg->dtype;
+    rec->k = cfg->k;
+    rec->steps = T;
+    rec->consumed = 0;
+    return FDTD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -453,57 +508,8 @@ int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const 
     if (rc) return rc;
     if (!eps || !fields || !psi || !store || !workspace || !loss || !rec)
         return fail(FDTD_EINVAL, "fdtd_forward: eps, fields, psi, store, workspace, loss and rec must not be NULL");
-    hipStream_t s = (hipStream_t)stream;
-    char* ws = (char*)workspace;
-    Grid g = pl.g;
-    g.coef = (const float*)(ws + pl.ws_coef);
-    g.src_profile = (const float*)(ws + pl.ws_profile);
-    g.msrc_profile = (const float*)(ws + pl.ws_mprofile);
-    double* partials = (double*)(ws + pl.ws_partials);
-    float* staging = (float*)(ws + pl.ws_staging);
-
-    // coefficient tables and source profile: staged through a host buffer that
-    // outlives the (pageable, staged-before-return) asynchronous copy
-    static thread_local std::vector<char> host;
-    host.assign(pl.ws_partials, 0);
-    std::memcpy(host.data() + pl.ws_coef, pl.coef.data(), pl.coef.size() * 4);
-    std::memcpy(host.data() + pl.ws_profile, prob->src_profile, (size_t)pl.src_volume * 4);
-    if (pl.msrc_volume > 0)
-        std::memcpy(host.data() + pl.ws_mprofile, prob->msrc_profile, (size_t)pl.msrc_volume * 4);
-    if (hipMemcpyAsync(ws, host.data(), pl.ws_partials, hipMemcpyHostToDevice, s) != hipSuccess)
-        return fail(FDTD_EHIP, "fdtd_forward: upload of coefficient tables failed");
-
-    const int64_t N = g.N;
-    const int T = prob->steps, k = cfg->k;
-    // ping-pong field buffers; the parity of T picks the start so that the
-    // final state lands in the caller's buffer
-    float* F[2] = {fields, (float*)(ws + pl.ws_fields)};
-    const int start = T & 1;
-    const bool fp8 = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED && g.vps > 0;
-    const float* wave = prob->src_wave;
-    auto mwave = [&](int n) { return pl.msrc_volume > 0 ? prob->msrc_wave[n] : 0.0f; };
-    auto enqueue = [&](hipStream_t q) {
-        launch_fill(F[start], 6 * N, 0.0f, q);
-        launch_fill(psi, 2 * (long long)pl.psi_floats, 0.0f, q);
-        for (int n = 0; n < T; ++n) {
-            const int slice = ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1;
-            const float* in = F[(start + n) & 1];
-            float* out = F[(start + n + 1) & 1];
-            launch_fwd_step(g, pl.fwd, in, out, psi, n & 1, eps, wave[n], mwave(n),
-                            partials + (int64_t)n * pl.per_step, store, staging, slice, q);
-            if (slice >= 0 && fp8) launch_rec_quant(g, staging, store, slice, q);
-        }
-        launch_loss_final(partials, T, pl.per_step, loss, loss_series, q);
-    };
-    rc = run_sequence(call_key(pl, 0, cfg, {eps, fields, psi, store, workspace, loss, loss_series}), s, enqueue,
-                      "fdtd_forward");
-    if (rc) return rc;
-    rec->problem_hash = pl.hash;
-    rec->dtype = cfg->dtype;
-    rec->k = cfg->k;
-    rec->steps = T;
-    rec->consumed = 0;
-    return FDTD_OK;
+    return forward_with(pl, prob, cfg, eps, fields, psi, store, (char*)workspace, loss, loss_series, rec,
+                        (hipStream_t)stream, true, "fdtd_forward");
 }
 
 int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const float* eps, float* fields,
@@ -533,6 +539,7 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
     const float* wave = prob->src_wave;
     auto mwave = [&](int n) { return pl.msrc_volume > 0 ? prob->msrc_wave[n] : 0.0f; };
     auto enqueue = [&](hipStream_t q) {
+        put_tables(pl, prob, ws, q);
         launch_fill(Fa[0], 6 * N, 0.0f, q);
         launch_fill(adj_psi, 2 * (long long)pl.psi_floats, 0.0f, q);
         launch_fill_f64(grad_eps, (long long)pl.info.design_cells, 0.0, q);

@@ -393,7 +393,7 @@ __device__ inline int slab_coord(int i, int n, int P) {   // -1 outside the slab
 // ----------------------------------------------------------------------------
 enum KernelKind {
     K_FILL = 0, K_FWD_STEP, K_REC_QUANT, K_LOSS_FINAL, K_INJECT, K_PRIM_REV, K_ADJ_STEP, K_SCALE_GRAD,
-    K_CODEC, K_NUM_KINDS
+    K_CODEC, K_PUT, K_NUM_KINDS
 };
 
 // Defined in api.hip: hands out an event pair when timing is enabled.
@@ -409,6 +409,8 @@ inline void launch_kernel(int kind, Kernel kernel, dim3 grid, dim3 block, hipStr
 }
 
 // Launch wrappers (defined with the kernels)
+constexpr int PUT_CHUNK = 896;        // floats carried by one k_put launch (3.5 KB of arguments)
+void launch_put(float* dst, const float* host, long long n, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 struct Tiling;

@@ -16,6 +16,9 @@
 #define FDTD_ST_AUX FDTD_FWD_ST_AUX
 #include "march.h"
 
+#include <algorithm>
+#include <cstring>
+
 namespace fdtd {
 
 __global__ void k_fill(float* p, long long n, float v) {
@@ -28,6 +31,27 @@ __global__ void k_fill_f64(double* p, long long n, double v) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long stride = (long long)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = v;
+}
+
+// Host values written into device memory by kernel launches that carry them as
+// arguments (PUT_CHUNK floats per launch): no host staging buffer and no copy from
+// pageable memory, and a captured graph holds the values themselves.
+struct PutChunk {
+    float v[PUT_CHUNK];
+};
+
+__global__ __launch_bounds__(256) void k_put(float* __restrict__ dst, int n, PutChunk c) {
+    for (int i = threadIdx.x; i < n; i += 256) dst[i] = c.v[i];
+}
+
+void launch_put(float* dst, const float* host, long long n, hipStream_t s) {
+    for (long long o = 0; o < n; o += PUT_CHUNK) {
+        const int m = (int)std::min<long long>(PUT_CHUNK, n - o);
+        PutChunk c;
+        std::memcpy(c.v, host + o, (size_t)m * sizeof(float));
+        std::memset(c.v + m, 0, (size_t)(PUT_CHUNK - m) * sizeof(float));
+        launch_kernel(K_PUT, k_put, dim3(1), dim3(256), s, dst + o, m, c);
+    }
 }
 
 void launch_fill(float* p, long long n, float v, hipStream_t s) {

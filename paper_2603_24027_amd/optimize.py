@@ -7,13 +7,24 @@ storage.  This module builds the same kind of loop around ``FDTDGrad``:
     rho (free variables, design box)
       -> s = sigmoid(rho)                               in (0, 1)
       -> f = GaussianBlur_sigma(s)                      minimum feature size (edges replicated)
-      -> p = (tanh(beta eta) + tanh(beta (f - eta))) / (tanh(beta eta) + tanh(beta (1 - eta)))
+      -> p = projection of f at level eta, sharpness beta (below)
       -> eps = eps_lo + (eps_hi - eps_lo) p             written into the design box
-      -> L = detector energy (the library's loss), maximised
+      -> L = the library's loss (detector energy or flux), maximised
 
-with NAdam and a linear learning-rate warm-up.  The filter, projection and
-optimiser are small torch operations on the design box; every forward and
-gradient evaluation of the field problem runs in the HIP library.
+with NAdam (Adam with Nesterov momentum) and a linear learning-rate warm-up.
+The paper's schedule keeps beta = 1 for the first 40 iterations and then
+projects at beta = infinity with a subpixel-smoothed projection, whose
+gradient does not vanish at the material interface (Section 3).  Finite beta
+uses the tanh projection
+      p = (tanh(beta eta) + tanh(beta (f - eta))) / (tanh(beta eta) + tanh(beta (1 - eta)));
+beta = infinity uses the fill fraction of each cell by the region f > eta with
+the interface taken as the plane through the cell that the filtered field's
+local gradient gives: signed distance d = (f - eta) / |grad f| (cells), and
+      p = clamp(1/2 + d, 0, 1),
+a one-cell linear ramp across the interface (exact for interfaces normal to an
+axis), binary away from it.  The filter, projection and optimiser are small
+torch operations on the design box; every forward and gradient evaluation of
+the field problem runs in the HIP library.
 """
 
 from __future__ import annotations
@@ -53,9 +64,20 @@ def blur3d(x: torch.Tensor, sigma: float) -> torch.Tensor:
 
 
 def project(f: torch.Tensor, beta: float, eta: float = 0.5) -> torch.Tensor:
-    """Smoothed threshold projection of f in [0, 1] at level eta and sharpness beta (maps 0->0, 1->1)."""
+    """Threshold projection of f in [0, 1] at level eta: tanh with sharpness beta (maps 0->0,
+    1->1), or for beta = infinity the subpixel-smoothed fill fraction (module docstring)."""
+    if math.isinf(beta):
+        return project_subpixel(f, eta)
     a = math.tanh(beta * eta)
     return (a + torch.tanh(beta * (f - eta))) / (a + math.tanh(beta * (1.0 - eta)))
+
+
+def project_subpixel(f: torch.Tensor, eta: float = 0.5) -> torch.Tensor:
+    """beta = infinity: fill fraction clamp(1/2 + (f - eta) / |grad f|, 0, 1) of each cell, the
+    gradient by central differences (one-sided at the box edges, unit cell size)."""
+    grads = torch.gradient(f, spacing=1.0, edge_order=1)
+    norm = torch.sqrt(sum(g * g for g in grads) + 1e-12)
+    return torch.clamp(0.5 + (f - eta) / norm, 0.0, 1.0)
 
 
 class DesignLoop:
@@ -68,7 +90,8 @@ class DesignLoop:
 
     def __init__(self, problem, dtype: str = "fp32", k: int = 1, sigma: float = 3.0, beta: float = 8.0,
                  eta: float = 0.5, eps_range=(1.0, 12.25), lr: float = 0.1, warmup: int = 10, seed: int = 0,
-                 device="cuda", rho0: Optional[torch.Tensor] = None):
+                 device="cuda", rho0: Optional[torch.Tensor] = None, beta_after: Optional[float] = None,
+                 switch_at: int = 40):
         self.device = torch.device(device)
         self.grad = Gradient(problem, dtype, k, device=self.device)
         self.background = torch.from_numpy(problem.eps).to(self.device)
@@ -78,6 +101,8 @@ class DesignLoop:
             rho0 = 0.1 * torch.randn(shape, generator=g, dtype=torch.float64)
         self.rho = rho0.to(self.device, torch.float64).clone().requires_grad_(True)
         self.sigma, self.beta, self.eta = sigma, beta, eta
+        # schedule: `beta` for the first `switch_at` iterations, then `beta_after` (if given)
+        self.beta_first, self.beta_after, self.switch_at = beta, beta_after, int(switch_at)
         self.lo, self.hi = float(eps_range[0]), float(eps_range[1])
         self.opt = torch.optim.NAdam([self.rho], lr=lr)
         self.warmup = max(1, int(warmup))
@@ -90,7 +115,13 @@ class DesignLoop:
         p = project(blur3d(s, self.sigma), self.beta, self.eta)
         return self.lo + (self.hi - self.lo) * p
 
+    def beta_at(self, iteration: int) -> float:
+        if self.beta_after is None or iteration < self.switch_at:
+            return self.beta_first
+        return self.beta_after
+
     def step(self) -> float:
+        self.beta = self.beta_at(self.iteration)
         for group in self.opt.param_groups:
             group["lr"] = self.lr * min(1.0, (self.iteration + 1) / self.warmup)
         self.opt.zero_grad(set_to_none=True)

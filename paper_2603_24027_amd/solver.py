@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import FdtdProblem, FdtdRecord, FdtdStoreCfg, FdtdStoreInfo, check, load
+from ._lib import FDTD_ENONFINITE, FDTD_ESTATE, FdtdError, FdtdProblem, FdtdRecord, FdtdStoreCfg, FdtdStoreInfo, \
+    check, load
 
 STORE_DTYPES = {
     "fp32": _lib.STORE_FP32,
@@ -138,6 +139,11 @@ class Gradient:
             self.buf.grad = torch.empty(self.problem.design_shape, dtype=torch.float64, device=dev)
         self.record = FdtdRecord()
         self.eps = None
+        self.generation = 0              # forward calls so far (FDTDGrad ties a backward to its forward)
+        # persistent buffers of FDTDGrad: the full eps map and the upstream gradient scale keep
+        # their device addresses across iterations, so repeated calls replay the same graphs
+        self.eps_buf = None
+        self.scale_buf = torch.ones((), dtype=torch.float64, device=dev) if with_backward else None
 
     @property
     def storage_bytes(self) -> int:
@@ -148,6 +154,7 @@ class Gradient:
         assert eps.dtype == torch.float32 and eps.is_contiguous() and eps.device.type == "cuda"
         assert tuple(eps.shape) == self.problem.shape
         self.eps = eps
+        self.generation += 1
         b = self.buf
         check(load().fdtd_forward(
             ctypes.byref(self.problem.c), ctypes.byref(self.cfg), eps.data_ptr(), b.fields.data_ptr(),
@@ -155,6 +162,16 @@ class Gradient:
             b.series.data_ptr() if b.series is not None else None, ctypes.byref(self.record),
             _stream_handle(self.device)))
         return b.loss
+
+    def loss_value(self) -> float:
+        """The loss of the last forward call as a Python float (waits for the device).
+        Raises FdtdError(FDTD_ENONFINITE) when it is NaN or infinite, e.g. after a
+        non-finite or non-positive eps."""
+        v = float(self.buf.loss.item())
+        if not np.isfinite(v):
+            raise FdtdError(FDTD_ENONFINITE, "loss of %s is %r (check eps: finite and > 0)"
+                            % (getattr(self.problem.desc, "name", "problem"), v))
+        return v
 
     def backward(self, grad_scale: Optional[torch.Tensor] = None) -> torch.Tensor:
         b = self.buf
@@ -179,23 +196,35 @@ class FDTDGrad(torch.autograd.Function):
 
     eps_design: float32 design-box tensor [dz, dy, dx]; eps_background: float32
     full map [nz, ny, nx] (its design box is overwritten by eps_design).
-    The backward runs the library's time-reversed pass; calling backward a
-    second time on the same forward raises (the fields were reversed).
+    The forward reads the loss back and raises FdtdError(FDTD_ENONFINITE) when it
+    is not finite.  The backward runs the library's time-reversed pass; it raises
+    FdtdError(FDTD_ESTATE) when called a second time on the same forward (the
+    fields were reversed) or after a later forward on the same grad_obj (its
+    fields, store and eps now belong to that call).
     """
 
     @staticmethod
     def forward(ctx, eps_design, grad_obj: Gradient, eps_background):
-        eps = eps_background.detach().to(torch.float32).clone().contiguous()
+        if grad_obj.eps_buf is None:
+            grad_obj.eps_buf = torch.empty(grad_obj.problem.shape, dtype=torch.float32, device=grad_obj.device)
+        eps = grad_obj.eps_buf
+        eps.copy_(eps_background.detach())
         eps[grad_obj.problem.design_slices()] = eps_design.detach().to(torch.float32)
         loss = grad_obj.forward(eps).clone()
+        grad_obj.loss_value()                      # raises on a non-finite loss
         ctx.grad_obj = grad_obj
+        ctx.generation = grad_obj.generation
         ctx.in_dtype = eps_design.dtype
         return loss
 
     @staticmethod
     def backward(ctx, grad_loss):
-        g = ctx.grad_obj.backward(grad_scale=grad_loss.detach().to(torch.float64).reshape(()).contiguous())
-        return g.to(ctx.in_dtype), None, None
+        gobj = ctx.grad_obj
+        if gobj.generation != ctx.generation:
+            raise FdtdError(FDTD_ESTATE, "a later forward on the same Gradient replaced this loss's fields and store")
+        gobj.scale_buf.copy_(grad_loss.detach().reshape(()))
+        g = gobj.backward(grad_scale=gobj.scale_buf)
+        return g.to(ctx.in_dtype, copy=True), None, None
 
 
 def codec_roundtrip(values: torch.Tensor, dtype: str, n_blocks: int):

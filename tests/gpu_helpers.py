@@ -38,3 +38,42 @@ def rel(a, b):
     a = np.asarray(a, np.float64).ravel()
     b = np.asarray(b, np.float64).ravel()
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+STORE_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
+
+
+def store_layout(gobj):
+    """(bytes per value, bytes between kept steps, byte offset of the FP8 scale table) of the
+    interface store, as include/fdtd.h lays it out."""
+    nb = STORE_BYTES.get(gobj.dtype, 1)
+    vps = int(gobj.info.values_per_slice)
+    stride = (vps * nb + 255) // 256 * 256
+    return nb, stride, int(gobj.info.slices) * stride
+
+
+def block_lengths(prob):
+    """Values of the 12 (face, component) blocks of one kept step, in store order."""
+    P = prob.pml
+    mx, my, mz = prob.nx - 2 * P, prob.ny - 2 * P, prob.nz - 2 * P
+    ax, ay, az = my * mz, mx * mz, mx * my
+    return [ax, ax, ay, ay, az, az] * 2
+
+
+def store_slice(gobj, j):
+    """The 12 blocks of kept step j (the j-th kept step counted back from the last time step)
+    as numpy arrays of raw codes (float32 for FP32, uint16 for 16-bit, uint8 for 8-bit types),
+    and the 12 FP8 scales (None for the other types)."""
+    nb, stride, scale_off = store_layout(gobj)
+    vps = int(gobj.info.values_per_slice)
+    raw = gobj.buf.store[j * stride: j * stride + vps * nb].cpu().numpy()
+    view = {4: np.float32, 2: np.uint16, 1: np.uint8}[nb]
+    vals = raw.view(view)
+    out, o = [], 0
+    for n in block_lengths(gobj.problem.desc):
+        out.append(vals[o:o + n])
+        o += n
+    scales = None
+    if gobj.dtype == "fp8_e4m3_scaled":
+        scales = gobj.buf.store[scale_off + j * 48: scale_off + (j + 1) * 48].cpu().numpy().view(np.float32)
+    return out, scales

@@ -77,3 +77,27 @@ def test_every_workload_and_crop_resolves():
     for name, crop in bench.CROPS.items():
         big, small = w.make(bench.WORKLOADS[name][0]), w.make(crop)
         assert (small.nx, small.ny, small.nz) == (128, 128, 128) and small.pml == big.pml
+
+
+def test_default_workload_is_hbm_bound_with_both_forms_and_a_crop():
+    # the headline runs the 256x256x128 slab (working set far above the 256 MB Infinity Cache),
+    # times FP32 every step beside FP8 k = 16 (exactly 64x: 16 divides 4000) and reports the
+    # gradient errors on the oracle-checked 128^3 crop of the same recipe
+    name = bench.DEFAULT_WORKLOAD
+    assert name not in bench.CACHE_RESIDENT
+    prob = w.make(bench.WORKLOADS[name][0])
+    per_step = 52 * prob.cells            # both field buffers and eps touched by one forward step
+    assert per_step > 1.5 * 256e6
+    assert bench.COMPRESSED[name][0] == ("fp8_e4m3_scaled", 16) and prob.steps % 16 == 0
+    crop = w.make(bench.CROPS[name])
+    assert crop.steps % 16 == 0 and crop.wavelength == prob.wavelength
+    assert crop.design_shape == prob.design_shape and crop.pml == prob.pml
+
+
+def test_cpu_sample_is_bounded_and_host_is_described():
+    for preset in ("c2", "c4", "c5"):
+        p = w.make(preset)
+        steps = bench.cpu_sample_steps(p.cells)
+        assert 1 <= steps and p.cells * steps <= 7e7
+    model, ncpu, usable = bench.host_description()
+    assert isinstance(model, str) and model and ncpu >= 1 and 1 <= usable <= ncpu

@@ -138,8 +138,10 @@ def test_c2_compressed_storage_and_agreement():
 
 
 def test_paper_regime_fp8_k16_keeps_gradient_direction():
-    """At ~136 steps per period (the paper's Section 2 example), FP8 with k = 16 (64x)
-    keeps the gradient direction of full FP32 storage (Section 3)."""
+    """At ~136 steps per period (the paper's Section 2 example), FP8 with k = 16 (63.5x here:
+    16 does not divide 1000) keeps the direction of the full-FP32-storage gradient to cosine
+    >= 0.99 (0.9986 measured, limited by the linear interpolation in time; Section 3).  This
+    bar is a regression check, not the 0.999 accuracy target, which this setting misses."""
     require_gpu()
     prob = w.c3p()
     say("c3p (lambda 77.5 cells): fp8 k=16 vs fp32 k=1")
@@ -194,20 +196,42 @@ def test_c2pw_fp32_gradient_matches_fp64_oracle():
     assert r <= 1e-5 and c >= 1 - 1e-9
 
 
-# At a 30-cell wavelength the step is 0.99/sqrt(3) of a cell, so a period spans about 52
-# steps: k = 16 keeps about 3.3 samples per period and the linear-in-time interpolation,
-# not the FP8 rounding, bounds the agreement (cosine 0.97 measured; 0.95 is the bar).
-@pytest.mark.parametrize("dtype,k,cos_min", [("fp32", 1, 1 - 1e-9), ("bf16", 4, 0.999),
-                                             ("fp8_e4m3_scaled", 16, 0.95)])
-def test_c5_crop_gradient_vs_fp64_oracle(dtype, k, cos_min):
-    # the slab-waveguide recipe of the 512x512x256 problem on a 128^3 crop, against the exact gradient
+# The slab-waveguide recipes of the 256x256x128 (c4, c4p) and 512x512x256 (c5) problems on
+# 128^3 crops, against the exact gradient.  At a 30-cell wavelength a period spans about 52
+# steps: k = 16 keeps about 3.3 samples per period and the linear-in-time interpolation, not
+# the FP8 rounding, bounds the agreement (cosine 0.97 measured on c5crop; 0.95 is the bar).
+# At 77.5 cells (c4pcrop, ~136 steps per period, the paper's sampling) the bar is the
+# measured value rounded down: it is below the 0.999 target, which linear interpolation
+# at k = 16 does not reach.
+CROP_CASES = [("c5crop", "fp32", 1, 1 - 1e-9), ("c5crop", "bf16", 4, 0.999), ("c5crop", "fp8_e4m3_scaled", 16, 0.95),
+              ("c4crop", "fp32", 1, 1 - 1e-9), ("c4crop", "bf16", 4, 0.999), ("c4crop", "fp8_e4m3_scaled", 16, 0.9),
+              ("c4pcrop", "fp32", 1, 1 - 1e-9), ("c4pcrop", "fp8_e4m3_scaled", 8, 0.999),
+              ("c4pcrop", "fp8_e4m3_scaled", 16, 0.99)]
+
+
+@pytest.mark.parametrize("preset,dtype,k,cos_min", CROP_CASES)
+def test_crop_gradient_vs_fp64_oracle(preset, dtype, k, cos_min):
     require_gpu()
-    prob = w.c5_crop(seed=0)
+    prob = w.make(preset, seed=0)
     exact = _oracle_gradient(prob.name, 0)
-    g = gpu_run(prob, dtype, k, keep_fields=False)["grad"]
+    out = gpu_run(prob, dtype, k, keep_fields=False)
+    g = out["grad"]
     r, c = metrics.rel_l2(g, exact), metrics.cosine_similarity(g, exact)
-    say("c5 crop %s k=%d vs FP64 oracle: cosine %.9f rel-L2 %.3e" % (dtype, k, c, r))
+    ratio = 32 / pk.STORAGE_BITS[dtype] * k
+    say("%s %s k=%d (%.0fx smaller) vs FP64 oracle: cosine %.9f rel-L2 %.3e" % (preset, dtype, k, ratio, c, r))
+    if k > 1:
+        assert prob.steps % k == 0
+        assert out["info"].payload_bytes * ratio == store_fp32_bytes(prob)
     assert c >= cos_min
     if dtype == "fp32":
         assert r <= 1e-5
+        cell = float(np.max(np.abs(g - exact)) / np.max(np.abs(exact)))
+        say("  per-cell max|d|/max|g| %.3e" % cell)
+        assert cell <= 1e-5
+
+
+def store_fp32_bytes(prob):
+    P = prob.pml
+    m = (prob.nx - 2 * P, prob.ny - 2 * P, prob.nz - 2 * P)
+    return 4 * (m[1] * m[2] + m[0] * m[2] + m[0] * m[1]) * 4 * prob.steps
 

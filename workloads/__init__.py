@@ -260,6 +260,26 @@ def c4(seed: int = 0, steps: int = 4000, wavelength: float = 30.0) -> Problem:
                         seed=seed)
 
 
+def c4p(seed: int = 0, steps: int = 4000) -> Problem:
+    """c4 at lambda 77.5 cells (~136 steps per period, the sampling of the paper's Section 2
+    example); 16 divides the 4000 steps, so FP8 with k = 16 stores exactly 1/64 of FP32."""
+    return replace(c4(seed=seed, steps=steps, wavelength=77.5), name="c4p_slab_256x256x128_lambda77")
+
+
+def c4_crop(seed: int = 0, steps: int = 2000, wavelength: float = 30.0) -> Problem:
+    """The c4 recipe on a 128^3 grid (x-y cropped to 128 x 128, z kept): 12-cell CPML, the
+    same slab, sheet plane, waist and 64x64x8 design box, output plane 20 cells before the
+    +x face; 2000 steps (16 divides it)."""
+    return slab_problem("c4crop_slab_128cube", (128, 128, 128), 12, steps, 100, 16.0, wavelength,
+                        (53, 75), (32, 32, 67), (96, 96, 75), (108, 32, 32), (109, 96, 96),
+                        seed=seed)
+
+
+def c4p_crop(seed: int = 0, steps: int = 2000) -> Problem:
+    """c4_crop at lambda 77.5 cells (the 128^3 crop of c4p)."""
+    return replace(c4_crop(seed=seed, steps=steps, wavelength=77.5), name="c4pcrop_slab_128cube_lambda77")
+
+
 def c5(seed: int = 0, steps: int = 8000, wavelength: float = 30.0) -> Problem:
     """512x512x256 slab waveguide, 16-cell CPML, 8000 steps, 128x128x16 design."""
     return slab_problem("c5_slab_512x512x256", (512, 512, 256), 16, steps, 200, 32.0, wavelength,
@@ -317,7 +337,8 @@ def ragged(seed: int = 0, steps: int = 40) -> Problem:
 
 
 PRESETS = {
-    "c1": c1, "c2": c2, "c3p": c3p, "c4": c4, "c5": c5, "c5crop": c5_crop,
+    "c1": c1, "c2": c2, "c3p": c3p, "c4": c4, "c4p": c4p, "c4crop": c4_crop, "c4pcrop": c4p_crop,
+    "c5": c5, "c5crop": c5_crop,
     "tiny": tiny, "ragged": ragged, "c2pw": c2pw, "tiny_pw": tiny_pw,
 }
 
