@@ -2,7 +2,7 @@
 
 Recorder (Section 2: interface slices, bit-width reduction, subsampling):
   * the FP32 store of every kept step holds the oracle's interface values, element by
-    element, to 2e-5 of the block's largest magnitude over the run (FP32 against FP64
+    element, to 3e-5 of the block's largest magnitude over the run (FP32 against FP64
     arithmetic);
   * the forward does not depend on the storage type (final fields bitwise equal), so the
     FP32 store of the same problem holds exactly the values every other recorder
@@ -44,7 +44,8 @@ def _codes_match_fp32_store(prob, ref, dtype, k, kept):
     """Every block of the kept steps `kept` of a (dtype, k) recording equals the oracle's
     encoding of the FP32 (k = 1) store's values of the same time step."""
     obj = _forward(prob, dtype, k)
-    assert torch.equal(obj.buf.fields, ref.buf.fields), "the forward must not depend on the storage type"
+    for a, b in zip(obj.fields(), ref.fields()):
+        assert torch.equal(a, b), "the forward must not depend on the storage type"
     mode = ORACLE_MODE[dtype]
     for j in kept:
         blocks, scales = store_slice(obj, j)
@@ -82,7 +83,7 @@ def test_fp32_store_holds_oracle_interface_values(case):
             got = blocks[b].astype(np.float64)
             err = np.max(np.abs(got - want)) / max(scale[b], 1e-30)
             worst = max(worst, err)
-            assert err <= 2e-5, (case, n, b, err)
+            assert err <= 3e-5, (case, n, b, err)
     say("  worst block max|d| / max over the run of |ref| %.3e" % worst)
 
 
