@@ -218,6 +218,29 @@ FDTD_API int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cf
                  double* loss, double* loss_series, fdtd_record_t* rec, void* stream);
 
 /*
+ * fdtd_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops or harnesses that forbid hipMalloc): the same
+ * arguments, kernels and results as fdtd_forward (bit for bit), without the
+ * workspace argument.  Its workspace is a device array of the library,
+ * FDTD_NOALLOC_SCRATCH_BYTES long, which every GPU the library runs on holds
+ * from the library's load until the process ends; the call allocates nothing
+ * (no hipMalloc, no graph instantiation: it always enqueues its launches
+ * directly).
+ *   Limit: workspace_bytes - fields_bytes of fdtd_store_info_t (the tables, loss
+ *   partials, recorder staging and one ping-pong field buffer) must not exceed
+ *   FDTD_NOALLOC_SCRATCH_BYTES (a 128^3 grid fits); larger problems return
+ *   FDTD_EINVAL before any HIP call.
+ *   Sharing: every call on one GPU uses that GPU's one array, and nothing in it
+ *   outlives the call's kernels: calls whose kernels overlap on one GPU (other
+ *   streams, other host threads) race and must be serialised by the caller.
+ * The record it returns feeds fdtd_backward as fdtd_forward's does.
+ */
+#define FDTD_NOALLOC_SCRATCH_BYTES (64u << 20)
+FDTD_API int fdtd_forward_noalloc(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg,
+                 const float* eps, float* fields, float* psi, void* store,
+                 double* loss, double* loss_series, fdtd_record_t* rec, void* stream);
+
+/*
  * Time-reversed gradient pass (Section 1: backwards from the final step with
  * one extra simulation; Section 2: interface fields injected as sources).
  *   fields      device, in: the final state left by fdtd_forward; destroyed

@@ -75,8 +75,9 @@ class FdtdKernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double)]
 
 
-EXPORTS = ("store_config", "fdtd_forward", "fdtd_backward", "fdtd_codec_roundtrip", "fdtd_timing_enable",
-           "fdtd_timing_read", "fdtd_set_graphs", "fdtd_strerror", "fdtd_last_error")
+EXPORTS = ("store_config", "fdtd_forward", "fdtd_forward_noalloc", "fdtd_backward", "fdtd_codec_roundtrip",
+           "fdtd_timing_enable", "fdtd_timing_read", "fdtd_set_graphs", "fdtd_strerror", "fdtd_last_error")
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _lib = None
 
@@ -99,13 +100,14 @@ def load() -> ctypes.CDLL:
     P = ctypes.POINTER
     lib.store_config.argtypes = [P(FdtdProblem), P(FdtdStoreCfg), P(FdtdStoreInfo)]
     lib.fdtd_forward.argtypes = [P(FdtdProblem), P(FdtdStoreCfg), vp, vp, vp, vp, vp, vp, vp, P(FdtdRecord), vp]
+    lib.fdtd_forward_noalloc.argtypes = [P(FdtdProblem), P(FdtdStoreCfg), vp, vp, vp, vp, vp, vp, P(FdtdRecord), vp]
     lib.fdtd_backward.argtypes = [P(FdtdProblem), P(FdtdStoreCfg), vp, vp, vp, vp, vp, vp, vp, vp,
                                   P(FdtdRecord), vp]
     lib.fdtd_codec_roundtrip.argtypes = [ctypes.c_int32, vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp]
     lib.fdtd_timing_enable.argtypes = [ctypes.c_int32]
     lib.fdtd_set_graphs.argtypes = [ctypes.c_int32]
     lib.fdtd_timing_read.argtypes = [P(FdtdKernelTime), ctypes.c_int32]
-    for name in ("store_config", "fdtd_forward", "fdtd_backward", "fdtd_codec_roundtrip",
+    for name in ("store_config", "fdtd_forward", "fdtd_forward_noalloc", "fdtd_backward", "fdtd_codec_roundtrip",
                  "fdtd_timing_enable", "fdtd_timing_read", "fdtd_set_graphs"):
         getattr(lib, name).restype = ctypes.c_int
     lib.fdtd_strerror.argtypes = [ctypes.c_int]

@@ -16,6 +16,12 @@
 
 using namespace fdtd;
 
+// Workspace of fdtd_forward_noalloc: one file-scope device array, which every device
+// the library runs on holds at its own address until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a stand-in): it
+// asks for the current device's address once (scratch_for_current_device) and uses that.
+static __device__ __align__(256) unsigned char scratch[FDTD_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -442,7 +448,29 @@ uint64_t call_key(const Plan& pl, int dir, const fdtd_store_cfg_t* cfg, std::ini
     return h;
 }
 
-// The forward time loop on the workspace `ws`.
+struct ScratchAddrs {
+    std::mutex mu;
+    void* ptr[64] = {};
+} g_scratch;
+
+int scratch_for_current_device(char** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(FDTD_EHIP, "fdtd_forward_noalloc: no usable current device");
+    std::lock_guard<std::mutex> lk(g_scratch.mu);
+    if (!g_scratch.ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FDTD_EHIP, "fdtd_forward_noalloc: address of the scratch array on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch.ptr[dev] = p;
+    }
+    *out = (char*)g_scratch.ptr[dev];
+    return FDTD_OK;
+}
+
+// The forward time loop on a workspace `ws` (the caller's, or the scratch array).
 int forward_with(const Plan& pl, const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const float* eps,
                  float* fields, float* psi, void* store, char* ws, double* loss, double* loss_series,
                  fdtd_record_t* rec, hipStream_t s, bool allow_graph, const char* what) {
@@ -510,6 +538,27 @@ int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const 
         return fail(FDTD_EINVAL, "fdtd_forward: eps, fields, psi, store, workspace, loss and rec must not be NULL");
     return forward_with(pl, prob, cfg, eps, fields, psi, store, (char*)workspace, loss, loss_series, rec,
                         (hipStream_t)stream, true, "fdtd_forward");
+}
+
+int fdtd_forward_noalloc(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const float* eps, float* fields,
+                         float* psi, void* store, double* loss, double* loss_series, fdtd_record_t* rec,
+                         void* stream) {
+    Plan pl;
+    int rc = make_plan(prob, cfg, &pl);
+    if (rc) return rc;
+    if (!eps || !fields || !psi || !store || !loss || !rec)
+        return fail(FDTD_EINVAL, "fdtd_forward_noalloc: eps, fields, psi, store, loss and rec must not be NULL");
+    const uint64_t need = pl.ws_fields + pl.info.fields_bytes;   // tables, partials, staging, one field buffer
+    if (need > (uint64_t)FDTD_NOALLOC_SCRATCH_BYTES)
+        return fail(FDTD_EINVAL, "fdtd_forward_noalloc: the problem needs %llu bytes of scratch, more than the %llu "
+                    "the library holds (workspace_bytes - fields_bytes must not exceed FDTD_NOALLOC_SCRATCH_BYTES)",
+                    (unsigned long long)need, (unsigned long long)FDTD_NOALLOC_SCRATCH_BYTES);
+    char* ws = nullptr;
+    rc = scratch_for_current_device(&ws);
+    if (rc) return rc;
+    // launched directly: graph capture and instantiation would allocate
+    return forward_with(pl, prob, cfg, eps, fields, psi, store, ws, loss, loss_series, rec, (hipStream_t)stream,
+                        false, "fdtd_forward_noalloc");
 }
 
 int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const float* eps, float* fields,

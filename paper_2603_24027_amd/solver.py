@@ -163,6 +163,21 @@ class Gradient:
             _stream_handle(self.device)))
         return b.loss
 
+    def forward_noalloc(self, eps: torch.Tensor) -> torch.Tensor:
+        """forward() through fdtd_forward_noalloc: the library's own device array serves as
+        the workspace (the problem must fit in it; see include/fdtd.h)."""
+        assert eps.dtype == torch.float32 and eps.is_contiguous() and eps.device.type == "cuda"
+        assert tuple(eps.shape) == self.problem.shape
+        self.eps = eps
+        self.generation += 1
+        b = self.buf
+        check(load().fdtd_forward_noalloc(
+            ctypes.byref(self.problem.c), ctypes.byref(self.cfg), eps.data_ptr(), b.fields.data_ptr(),
+            b.psi.data_ptr(), b.store.data_ptr(), b.loss.data_ptr(),
+            b.series.data_ptr() if b.series is not None else None, ctypes.byref(self.record),
+            _stream_handle(self.device)))
+        return b.loss
+
     def loss_value(self) -> float:
         """The loss of the last forward call as a Python float (waits for the device).
         Raises FdtdError(FDTD_ENONFINITE) when it is NaN or infinite, e.g. after a

@@ -139,3 +139,34 @@ def test_strerror_table():
     for code in range(0, -8, -1):
         assert lib.fdtd_strerror(code)
     assert lib.fdtd_strerror(-99) == b"unknown error"
+
+
+def test_noalloc_forward_validates_before_device_work():
+    # NULL buffers, then a problem whose workspace exceeds the library's array: both refused
+    # before any HIP call (non-NULL stand-in pointers are never dereferenced on this path)
+    lib = pk.load()
+    fake = ctypes.c_void_p(0x1000)
+    for prob, want in [(w.tiny(), None), (w.c4(steps=8), _lib.FDTD_EINVAL)]:
+        p = pk.Problem(prob)
+        cfg = _lib.FdtdStoreCfg(0, 1)
+        rec = _lib.FdtdRecord()
+        assert lib.fdtd_forward_noalloc(ctypes.byref(p.c), ctypes.byref(cfg), None, None, None, None, None, None,
+                                        ctypes.byref(rec), None) == _lib.FDTD_EINVAL
+        if want is not None:
+            info = pk.store_config(p, "fp32", 1)
+            assert info.workspace_bytes - info.fields_bytes > _lib.NOALLOC_SCRATCH_BYTES
+            rc = lib.fdtd_forward_noalloc(ctypes.byref(p.c), ctypes.byref(cfg), fake, fake, fake, fake, fake, None,
+                                          ctypes.byref(rec), None)
+            assert rc == want
+            assert "FDTD_NOALLOC_SCRATCH_BYTES" in lib.fdtd_last_error().decode()
+
+
+def test_noalloc_limit_matches_header():
+    text = open(HEADER).read()
+    m = re.search(r"#define FDTD_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_SCRATCH_BYTES
+    # a 128^3 problem fits (the header's claim), for every storage type
+    p = pk.Problem(w.c2())
+    for dtype in pk.STORE_DTYPES:
+        info = pk.store_config(p, dtype, 1)
+        assert info.workspace_bytes - info.fields_bytes <= _lib.NOALLOC_SCRATCH_BYTES
