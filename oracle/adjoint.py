@@ -133,18 +133,20 @@ def record_forward(solver: Solver, mode: str = "fp64", k: int = 1, steps: int = 
     return float(np.sum(losses)), losses, s, kept_H, kept_E
 
 
-def shell_at(n: int, T: int, k: int, kept: dict):
-    """Interpolated list of 6 shell blocks at step n (zero anchor at step -1)."""
+def shell_at(n: int, T: int, k: int, kept: dict, interp: int = 1):
+    """Interpolated list of 6 shell blocks at step n (zero anchor at step -1): linear in
+    time (interp 1, Section 2) or the cubic option (interp 3, store.cubic_nodes)."""
     any_blocks = next(iter(kept.values()))
+    rule = store.interpolate if interp == 1 else store.interpolate_cubic
     out = []
     for b in range(len(any_blocks)):
         per_step = {m: blocks[b] for m, blocks in kept.items()}
-        out.append(store.interpolate(n, T, k, per_step, np.zeros_like(any_blocks[b])))
+        out.append(rule(n, T, k, per_step, np.zeros_like(any_blocks[b])))
     return out
 
 
 def grad_time_reversal(problem, mode: str = "fp64", k: int = 1, match_fp32: bool = False,
-                       return_trace: bool = False):
+                       return_trace: bool = False, interp: int = 1):
     """(loss, dL/deps on the design box) by time reversal with (compressed) shell reinjection.
 
     With return_trace, also returns {n: (E^n, H^{n-1/2}) on the interior} as
@@ -161,12 +163,12 @@ def grad_time_reversal(problem, mode: str = "fp64", k: int = 1, match_fp32: bool
     for n in range(T - 1, -1, -1):
         seed(solver, a, s.E[(slice(None),) + solver.det_sl], s.H[(slice(None),) + solver.det_sl])
         if have_shell:
-            solver.put_shell_H(s, shell_at(n, T, k, kept_H))          # H^{n+1/2} on the low shell
+            solver.put_shell_H(s, shell_at(n, T, k, kept_H, interp))  # H^{n+1/2} on the low shell
         UJ = solver.e_inverse(s, n)                                     # E^n on I
         g += _grad_term(solver, a.E, UJ[(slice(None),) + solver.des_sl])
         adjoint_e_half(solver, a)
         if have_shell:
-            solver.put_shell_E(s, shell_at(n, T, k, kept_E))          # E^n on the high shell
+            solver.put_shell_E(s, shell_at(n, T, k, kept_E, interp))  # E^n on the high shell
         solver.h_inverse(s, n)                                          # H^{n-1/2} on I
         adjoint_h_half(solver, a)
         if return_trace:

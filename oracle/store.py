@@ -48,6 +48,46 @@ def interpolate(n: int, T: int, k: int, kept: dict, zero):
     return (1.0 - w) * v0 + w * v1
 
 
+def cubic_nodes(n: int, T: int, k: int):
+    """Nodes and weights of the cubic reconstruction at step n (an option beside the
+    paper's linear interpolation, not from the paper).
+
+    The nodes are the zero anchor -1 and the kept steps, in increasing time order.  For
+    n strictly between two neighbouring nodes, the four consecutive nodes with n in the
+    middle interval are used, shifted inward at either end of the run; the weights are
+    those of the Lagrange polynomial of degree 3 through them, evaluated at n.  Returns
+    [(node, weight)]; a kept n gives [(n, 1.0)].  With fewer than four nodes the linear
+    rule applies.
+    """
+    kept = sorted(kept_steps(T, k))
+    if n in kept:
+        return [(n, 1.0)]
+    nodes = [-1] + kept
+    if len(nodes) < 4:
+        n0, n1, w = bracket(n, T, k)
+        return [(n0, 1.0 - w), (n1, w)]
+    i = max(j for j in range(len(nodes)) if nodes[j] < n)       # nodes[i] < n < nodes[i + 1]
+    s = min(max(i - 1, 0), len(nodes) - 4)
+    sel = nodes[s:s + 4]
+    out = []
+    for a in sel:
+        w = 1.0
+        for b in sel:
+            if b != a:
+                w *= (n - b) / (a - b)
+        out.append((a, w))
+    return out
+
+
+def interpolate_cubic(n: int, T: int, k: int, kept: dict, zero):
+    """Value at step n from the kept values {step: array} by cubic_nodes; the anchor -1 is ``zero``."""
+    total = None
+    for node, w in cubic_nodes(n, T, k):
+        v = zero if node == -1 else kept[node]
+        total = w * v if total is None else total + w * v
+    return total
+
+
 def shell_values_per_step(nx: int, ny: int, nz: int, pml: int) -> int:
     """Tangential H on the 3 low faces + tangential E on the 3 high faces, interior extent."""
     if pml == 0:

@@ -245,3 +245,54 @@ def test_e3m4_definition_constants():
     assert codec.decode([0x10], fmt)[0] == 0.25          # smallest normal 2^(1-3)
     assert codec.decode([0x70], fmt)[0] == np.inf
     assert codec.encode(np.array([15.75, 15.7]), fmt).tolist() == [0x70, 0x6F]   # tie to even -> inf
+
+
+# --------------------------------------------------------------------------- cubic reconstruction option
+
+@pytest.mark.parametrize("T,k", [(37, 5), (64, 16), (10, 4), (1000, 16), (9, 3)])
+def test_cubic_reproduces_cubic_polynomials_through_the_anchor(T, k):
+    # degree-3 Lagrange interpolation is exact for cubics; the zero anchor at -1 is a node,
+    # so the polynomial must vanish there
+    p = lambda t: (t + 1.0) * (0.3 * t * t - 2.0 * t + 5.0)
+    kept = {n: np.array([p(n)]) for n in store.kept_steps(T, k)}
+    for n in range(T):
+        got = store.interpolate_cubic(n, T, k, kept, np.zeros(1))
+        assert abs(float(got[0]) - p(n)) <= 1e-9 * max(1.0, abs(p(n))), (T, k, n)
+
+
+def test_cubic_weights_partition_of_unity_and_kept_steps_exact():
+    for T, k in [(37, 5), (100, 8), (17, 16)]:
+        K = set(store.kept_steps(T, k))
+        for n in range(T):
+            nodes = store.cubic_nodes(n, T, k)
+            assert abs(sum(w for _, w in nodes) - 1.0) < 1e-12
+            if n in K:
+                assert nodes == [(n, 1.0)]
+            else:
+                assert all(a in K or a == -1 for a, _ in nodes)
+                assert min(a for a, _ in nodes) < n < max(a for a, _ in nodes)
+
+
+def test_cubic_midpoint_factor_closed_form():
+    # equally spaced nodes, n in the middle of the middle interval: weights (-1, 9, 9, -1)/16,
+    # so a cosine centred there comes back scaled by (9 cos(th/2) - cos(3 th/2)) / 8, th = w k
+    T, k, period = 1601, 16, 136.0
+    w = 2.0 * math.pi / period
+    n = T - 1 - 5 * k - k // 2                    # midway between kept steps, far from both ends
+    kept = {m: np.array([math.cos(w * (m - n))]) for m in store.kept_steps(T, k)}
+    got = float(store.interpolate_cubic(n, T, k, kept, np.zeros(1))[0])
+    th = w * k
+    assert abs(got - (9.0 * math.cos(th / 2) - math.cos(3 * th / 2)) / 8.0) < 1e-12
+    lin = float(store.interpolate(n, T, k, kept, np.zeros(1))[0])
+    assert abs(lin - math.cos(th / 2)) < 1e-12                 # the linear rule's factor
+    assert abs(1 - got) < 0.1 * abs(1 - lin)                    # an order of magnitude closer at 8.5 samples/period
+
+
+def test_cubic_falls_back_to_linear_with_few_nodes():
+    T, k = 9, 4                                                 # kept steps 8, 4, 0 plus the anchor: 4 nodes
+    assert len(store.cubic_nodes(2, T, k)) == 4
+    T, k = 5, 3                                                 # kept 4, 1 plus the anchor: 3 nodes -> linear
+    for n in range(T):
+        a = store.interpolate_cubic(n, T, k, {m: np.array([m * 1.0 + 1]) for m in store.kept_steps(T, k)}, np.zeros(1))
+        b = store.interpolate(n, T, k, {m: np.array([m * 1.0 + 1]) for m in store.kept_steps(T, k)}, np.zeros(1))
+        assert np.array_equal(a, b)
