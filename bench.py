@@ -56,8 +56,9 @@ WORKLOADS = {
 # workload -> its 128^3 crop, whose exact gradient the FP64 oracle stores (tests/golden)
 CROPS = {"c4": "c4crop", "c4p": "c4pcrop", "c5": "c5crop"}
 # storage settings timed beside the plain FP32 one (the first is reported as "compressed")
-COMPRESSED = {"c4": [("fp8_e4m3_scaled", 16), ("bf16", 4)], "c4p": [("fp8_e4m3_scaled", 16), ("bf16", 4)],
-              "c5": [("fp8_e4m3_scaled", 16), ("bf16", 4)]}
+# (storage type, k, interpolation in time: "linear" as in the paper, or the cubic option)
+_FP8_BF16 = [("fp8_e4m3_scaled", 16, "linear"), ("fp8_e4m3_scaled", 16, "cubic"), ("bf16", 4, "linear")]
+COMPRESSED = {"c4": _FP8_BF16, "c4p": _FP8_BF16, "c5": _FP8_BF16}
 # workloads whose working set fits the 256 MB Infinity Cache: their sweeps are not HBM-bound
 CACHE_RESIDENT = {"c2", "c3p", "c2pw", "c4crop", "c4pcrop", "c5crop"}
 DEFAULT_WORKLOAD = "c4"
@@ -205,7 +206,7 @@ def run_sweep(args, w, pk, torch, dev):
             row = {"cos_oracle": [], "rel_oracle": [], "cos_fp32": [], "rel_fp32": []}
             rate = None
             for s, (p, ref) in enumerate(zip(probs, refs)):
-                g = pk.Gradient(p, dtype, k, device=dev)
+                g = pk.Gradient(p, dtype, k, device=dev, interp=args.interp)
                 e = torch.from_numpy(p.eps).to(dev)
                 reps = 2 if s == 0 else 1          # seed 0 runs twice: the second call is timed
                 for r in range(reps):
@@ -222,7 +223,7 @@ def run_sweep(args, w, pk, torch, dev):
                     row["cos_oracle"].append(cosine(gr, exact[s]) if ok else float("nan"))
                     row["rel_oracle"].append(rel_l2(gr, exact[s]) if ok else float("nan"))
             info = pk.store_config(pk.Problem(probs[0]), dtype, k)
-            line = {"sweep": probs[0].name, "amplitude": A, "store_dtype": dtype, "k": k,
+            line = {"sweep": probs[0].name, "amplitude": A, "store_dtype": dtype, "k": k, "interp": args.interp,
                     "compression": round(full / info.payload_bytes, 3), "storage_GB": info.payload_bytes / 1e9,
                     "cos_vs_fp32_mean": float(np.mean(row["cos_fp32"])),
                     "rel_l2_vs_fp32_mean": float(np.mean(row["rel_fp32"])),
@@ -296,6 +297,8 @@ def main():
     ap.add_argument("--sweep-seeds", type=int, default=3)
     ap.add_argument("--sweep-types", default="", help="comma-separated storage types (default: all)")
     ap.add_argument("--sweep-k", default="", help="comma-separated subsampling factors (default: 1,2,4,8,16,32)")
+    ap.add_argument("--interp", default="linear", choices=["linear", "cubic"],
+                    help="interpolation in time of the skipped steps in --sweep runs")
     ap.add_argument("--amplitude", type=float, default=1.0,
                     help="scale of the source signal in --sweep runs (field units relative to the unscaled 8-bit ranges)")
     ap.add_argument("--design-lr", type=float, default=0.1)
@@ -342,8 +345,8 @@ def main():
 
     fwd_rev_ms = {}
 
-    def timed_run(dtype_, k_, steps, warmup):
-        gobj = pk.Gradient(prob, dtype_, k_, device=dev)
+    def timed_run(dtype_, k_, steps, warmup, interp_="linear"):
+        gobj = pk.Gradient(prob, dtype_, k_, device=dev, interp=interp_)
         for _ in range(warmup):
             gobj.forward(eps)
             gobj.backward()
@@ -360,7 +363,7 @@ def main():
             c.record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        fwd_rev_ms[(dtype_, k_)] = (float(np.mean([a.elapsed_time(b) for a, b, _ in marks])),
+        fwd_rev_ms[(dtype_, k_, interp_)] = (float(np.mean([a.elapsed_time(b) for a, b, _ in marks])),
                                     float(np.mean([b.elapsed_time(c) for _, b, c in marks])))
         return (t1 - t0), gobj
 
@@ -421,8 +424,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3),
-        "t_fwd_ms": round(fwd_rev_ms[(dtype, k)][0], 3),
-        "t_rev_ms": round(fwd_rev_ms[(dtype, k)][1], 3),
+        "t_fwd_ms": round(fwd_rev_ms[(dtype, k, "linear")][0], 3),
+        "t_rev_ms": round(fwd_rev_ms[(dtype, k, "linear")][1], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -446,16 +449,16 @@ def main():
 
     c_obj = None
     if not args.no_compressed:
-        for i, (cd, ck) in enumerate(COMPRESSED.get(args.workload, [("fp8_e4m3_scaled", 16)])):
+        for i, (cd, ck, ci) in enumerate(COMPRESSED.get(args.workload, [("fp8_e4m3_scaled", 16, "linear")])):
             # the same timed protocol on fewer gradients (the GPU time of the run stays bounded)
             c_steps, c_warm = min(args.steps, 5), min(args.warmup, 1)
-            c_el, obj = timed_run(cd, ck, c_steps, c_warm)
-            progress("compressed timed region (%s k=%d): %.3f s for %d gradients" % (cd, ck, c_el, c_steps))
-            rec = {"store_dtype": cd, "k": ck, "steps": c_steps, "warmup": c_warm,
+            c_el, obj = timed_run(cd, ck, c_steps, c_warm, ci)
+            progress("compressed timed region (%s k=%d %s): %.3f s for %d gradients" % (cd, ck, ci, c_el, c_steps))
+            rec = {"store_dtype": cd, "k": ck, "interp": ci, "steps": c_steps, "warmup": c_warm,
                    "value": round(cells * T * c_steps / c_el / 1e6, 1),
                    "ms_per_step": round(c_el / c_steps * 1e3, 3),
-                   "t_fwd_ms": round(fwd_rev_ms[(cd, ck)][0], 3),
-                   "t_rev_ms": round(fwd_rev_ms[(cd, ck)][1], 3),
+                   "t_fwd_ms": round(fwd_rev_ms[(cd, ck, ci)][0], 3),
+                   "t_rev_ms": round(fwd_rev_ms[(cd, ck, ci)][1], 3),
                    "boundary_store_GB": obj.info.payload_bytes / 1e9,
                    "storage_reduction": gobj.info.payload_bytes / obj.info.payload_bytes}
             g_ref = gobj.buf.grad.cpu().numpy()
@@ -479,11 +482,14 @@ def main():
                                          "truncated to %d time steps: %.1f s"
                                          % (prob.nx, prob.ny, prob.nz, steps_cpu, dt_cpu),
                                "cpu_model": model, "host_logical_cpus": ncpu, "usable_cpus": usable}
+    def form_name(d, kk, ip):
+        return "%s_k%d%s" % (d, kk, "" if ip == "linear" else "_" + ip)
+
     exact = oracle_gradient(prob.name, 0)
     if exact is not None:
-        errs = {"%s_k%d" % (dtype, k): gobj.buf.grad.cpu().numpy()}
+        errs = {form_name(dtype, k, "linear"): gobj.buf.grad.cpu().numpy()}
         if c_obj is not None:
-            errs["%s_k%d" % (c_obj.dtype, c_obj.k)] = c_obj.buf.grad.cpu().numpy()
+            errs[form_name(c_obj.dtype, c_obj.k, c_obj.interp)] = c_obj.buf.grad.cpu().numpy()
         out["grad_err_vs_fp64_oracle"] = {
             name: {"rel_l2": rel_l2(g, exact), "cosine": cosine(g, exact)} for name, g in errs.items()}
     if args.workload in CROPS and not args.no_crop:
@@ -493,12 +499,12 @@ def main():
         if cexact is not None:
             ce = torch.from_numpy(cprob.eps).to(dev)
             res = {"workload": cprob.name}
-            for cd, ck in [("fp32", 1)] + COMPRESSED.get(args.workload, []):
-                obj = pk.Gradient(cprob, cd, ck, device=dev)
+            for cd, ck, ci in [("fp32", 1, "linear")] + COMPRESSED.get(args.workload, []):
+                obj = pk.Gradient(cprob, cd, ck, device=dev, interp=ci)
                 obj.forward(ce)
                 gr = obj.backward().cpu().numpy()
-                res["%s_k%d" % (cd, ck)] = {"rel_l2": rel_l2(gr, cexact), "cosine": cosine(gr, cexact),
-                                            "boundary_store_GB": obj.info.payload_bytes / 1e9}
+                res[form_name(cd, ck, ci)] = {"rel_l2": rel_l2(gr, cexact), "cosine": cosine(gr, cexact),
+                                              "boundary_store_GB": obj.info.payload_bytes / 1e9}
                 del obj
             out["crop_grad_err_vs_fp64_oracle"] = res
             if "grad_err_vs_fp64_oracle" not in out:

@@ -136,12 +136,23 @@ typedef struct {
 
 /* Recorder configuration: storage type (FDTD_STORE_*) and subsampling k >= 1.
  * Kept steps: K = {T-1, T-1-k, ...} (ceil(T/k) of them); the reverse pass
- * rebuilds the others by linear interpolation between kept neighbours, with
- * an exact zero at step -1 (Section 2; Fig. 1b). */
+ * rebuilds the others by interpolation in time between kept steps, with an
+ * exact zero at step -1:
+ *   interp 0 or 1: linear between the two kept neighbours (Section 2; Fig. 1b);
+ *   interp 3:      cubic, the Lagrange polynomial through the four nearest nodes
+ *                  (kept steps and the zero anchor; n in the middle interval,
+ *                  shifted inward at the ends of the run; linear when fewer than
+ *                  four nodes exist).  An option beyond the paper's method: it only
+ *                  changes how fdtd_backward rebuilds the shell, not what is stored.
+ */
 typedef struct {
     int32_t dtype;
     int32_t k;
+    int32_t interp;
 } fdtd_store_cfg_t;
+
+#define FDTD_INTERP_LINEAR 1
+#define FDTD_INTERP_CUBIC  3
 
 /* Sizes the caller must allocate (bytes) and storage accounting. */
 typedef struct {
@@ -156,8 +167,9 @@ typedef struct {
     uint64_t psi_bytes;         /* forward PML auxiliaries (H side in two copies)        */
     uint64_t adj_psi_bytes;     /* backward PML auxiliaries (two copies, ping-pong)      */
     uint64_t workspace_bytes;   /* coefficient tables, source profile, loss partials,
-                                   recorder staging, and two more field buffers (the
-                                   ping-pong partners of fields and adj_fields)          */
+                                   recorder staging, the tiles' launch order, and two
+                                   more field buffers (the ping-pong partners of fields
+                                   and adj_fields), in that order                        */
     uint64_t design_cells;      /* cells of the design box (length of the gradient)      */
 } fdtd_store_info_t;
 

@@ -57,7 +57,11 @@ class FdtdProblem(ctypes.Structure):
 
 
 class FdtdStoreCfg(ctypes.Structure):
-    _fields_ = [("dtype", ctypes.c_int32), ("k", ctypes.c_int32)]
+    _fields_ = [("dtype", ctypes.c_int32), ("k", ctypes.c_int32), ("interp", ctypes.c_int32)]
+
+
+INTERP_LINEAR = 1
+INTERP_CUBIC = 3
 
 
 class FdtdStoreInfo(ctypes.Structure):

@@ -67,6 +67,7 @@ struct Plan {
     int rev_x0;                    // x origin of the primal-reversal tiles (128-byte aligned)
     fdtd_store_info_t info;
     uint64_t ws_coef = 0, ws_profile = 0, ws_partials = 0, ws_staging = 0, ws_fields = 0;
+    uint64_t ws_order_fwd = 0, ws_order_adj = 0;   // tile-order tables
     uint64_t psi_floats = 0;
     int per_step = 0;
     int64_t src_volume = 0;
@@ -150,6 +151,8 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     if (cfg->dtype < FDTD_STORE_FP32 || cfg->dtype > FDTD_STORE_FP8_E4M3FN)
         return fail(FDTD_ESTORE, "unknown storage type %d", cfg->dtype);
     if (cfg->k < 1) return fail(FDTD_ESTORE, "subsampling k must be >= 1 (got %d)", cfg->k);
+    if (cfg->interp != 0 && cfg->interp != FDTD_INTERP_LINEAR && cfg->interp != FDTD_INTERP_CUBIC)
+        return fail(FDTD_ESTORE, "interp must be 0 or 1 (linear) or 3 (cubic) (got %d)", cfg->interp);
 
     const int P = p->pml;
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
@@ -188,7 +191,6 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     const uint64_t vbytes = (uint64_t)storage_bytes(cfg->dtype);
     const uint64_t slices = ((uint64_t)p->steps + cfg->k - 1) / cfg->k;
     g.slice_stride = (long long)align_up(vps * vbytes, 256);
-    for (int b = 0; b < 12; ++b) g.rec_off[b] = P > 0 ? (uint32_t)block_offset(g, b) : 0u;
     g.scale_off = (long long)(slices * (uint64_t)g.slice_stride);
     g.dbx0 = p->det_lo[0] / BX; g.dnbx = (p->det_hi[0] - 1) / BX - g.dbx0 + 1;
     g.dby0 = p->det_lo[1] / BY; g.dnby = (p->det_hi[1] - 1) / BY - g.dby0 + 1;
@@ -204,6 +206,7 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     t.dty0 = p->det_lo[1] / t.ty; t.dnty = (p->det_hi[1] - 1) / t.ty - t.dty0 + 1;
     t.dtz0 = p->det_lo[2] / t.cz; t.dntz = (p->det_hi[2] - 1) / t.cz - t.dtz0 + 1;
     pl->per_step = t.dntx * t.dnty * t.dntz;
+    t.order = nullptr;
     for (int d = 0; d < 3; ++d) {
         pl->box_o[d] = P > 0 ? P - 1 : 0;
         pl->box_n[d] = P > 0 ? n[d] - 2 * P + 2 : n[d];
@@ -265,7 +268,9 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     pl->ws_staging = pl->ws_partials + align_up((uint64_t)p->steps * pl->per_step * 8, 256);
     const uint64_t staging =
         cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? align_up((uint64_t)rec_quant_scratch_floats(g) * 4, 256) : 0;
-    pl->ws_fields = pl->ws_staging + staging;
+    pl->ws_order_fwd = pl->ws_staging + staging;
+    pl->ws_order_adj = pl->ws_order_fwd + align_up(4ull * pl->fwd.count, 256);
+    pl->ws_fields = pl->ws_order_adj + align_up(4ull * pl->adj.count, 256);
     // second primal and second adjoint field buffers (ping-pong)
     in.workspace_bytes = pl->ws_fields + 2 * in.fields_bytes;
     in.design_cells = (uint64_t)(p->des_hi[0] - p->des_lo[0]) * (p->des_hi[1] - p->des_lo[1]) *
@@ -294,6 +299,38 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     return FDTD_OK;
 }
 
+// Launch order of a sweep's tiles (the device computes each tile's class again from its
+// coordinates; the order only decides where and beside what each block runs).  The
+// position p of a block goes to XCD p / (count / 8) (logical_tile), so the order is
+// dealt out in eight equal chunks: every chunk gets an eighth of each class's tiles
+// (classes differ in cost; in plain x-y-z order the z-slab tiles, the costliest, would
+// all land on the first and last XCD), and within a chunk the tiles come class by class,
+// each class in x-y-z order (neighbouring tiles share halo lines in that XCD's L2, and
+// the blocks running side by side mostly share one class's code).
+// which: 0 forward, 1 adjoint.
+void tile_order(const Plan& pl, int which, std::vector<int32_t>& out) {
+    const Tiling& t = which == 0 ? pl.fwd : pl.adj;
+    std::vector<int32_t> cls((size_t)t.count);
+    int counts[8] = {0};
+    for (int L = 0; L < t.count; ++L) {
+        const int tix = L % t.ntx, tiy = (L / t.ntx) % t.nty, tiz = L / (t.ntx * t.nty);
+        const int i0 = tix * TX, j0 = tiy * t.ty, k0 = tiz * t.cz;
+        const int c = slab_class(pl.g, i0 - 1, i0 + TX, j0 - 1, j0 + t.ty, k0 - 1, k0 + t.cz);
+        cls[(size_t)L] = c;
+        ++counts[c];
+    }
+    std::vector<int32_t> by_class[8];
+    for (int c = 0; c < 8; ++c) by_class[c].reserve((size_t)counts[c]);
+    for (int L = 0; L < t.count; ++L) by_class[cls[(size_t)L]].push_back(L);
+    out.clear();
+    out.reserve((size_t)t.count);
+    for (int x = 0; x < 8; ++x)
+        for (int c = 0; c < 8; ++c) {
+            const size_t n = by_class[c].size(), lo = n * x / 8, hi = n * (x + 1) / 8;
+            out.insert(out.end(), by_class[c].begin() + (long)lo, by_class[c].begin() + (long)hi);
+        }
+}
+
 // The CPML coefficient table and the source profiles into the workspace, written by
 // kernel launches that carry the values (so a captured graph holds them, and the
 // call reads no host memory after it returns).  Both directions write them, so a
@@ -304,10 +341,32 @@ void put_tables(const Plan& pl, const fdtd_problem_t* prob, char* ws, hipStream_
     if (pl.msrc_volume > 0) launch_put((float*)(ws + pl.ws_mprofile), prob->msrc_profile, pl.msrc_volume, q);
 }
 
-Interp interp_for(int n, int T, int k) {
+// Weights of the reinjection at reverse step n (kept steps T-1-j*k, j = 0 .. M-1, and the
+// zero anchor at -1).  Linear: the two kept neighbours.  Cubic (interp 3): the Lagrange
+// polynomial through the four consecutive nodes around n (times ascending: the anchor,
+// then the kept steps), with n in the middle interval unless that runs past either end
+// of the nodes; linear when there are fewer than four nodes.
+Interp interp_for(int n, int T, int k, int interp) {
     Interp q;
+    for (int t = 0; t < 4; ++t) { q.j[t] = -1; q.w[t] = 0.0f; }
     if ((T - 1 - n) % k == 0) {
-        q.j0 = -1; q.j1 = (T - 1 - n) / k; q.w0 = 0.0f; q.w1 = 1.0f;
+        q.j[0] = (T - 1 - n) / k;
+        q.w[0] = 1.0f;
+        return q;
+    }
+    const int M = (T + k - 1) / k;                 // kept steps
+    if (interp == FDTD_INTERP_CUBIC && M >= 3) {
+        const int nmin = T - 1 - (M - 1) * k;      // earliest kept step
+        auto node_time = [&](int i) { return i == 0 ? -1 : nmin + (i - 1) * k; };   // i = 0 .. M
+        const int i = n < nmin ? 0 : 1 + (n - nmin) / k;                           // node_time(i) < n < node_time(i+1)
+        const int s = std::min(std::max(i - 1, 0), M - 3);
+        for (int a = 0; a < 4; ++a) {
+            double w = 1.0;
+            for (int b = 0; b < 4; ++b)
+                if (b != a) w *= (double)(n - node_time(s + b)) / (double)(node_time(s + a) - node_time(s + b));
+            q.j[a] = s + a == 0 ? -1 : M - (s + a);   // slice of the node (the anchor has none)
+            q.w[a] = (float)w;
+        }
         return q;
     }
     const int j1 = (T - 1 - n) / k;
@@ -315,9 +374,8 @@ Interp interp_for(int n, int T, int k) {
     int n0 = n1 - k, j0 = j1 + 1;
     if (n0 < 0) { n0 = -1; j0 = -1; }
     const double w = (double)(n - n0) / (double)(n1 - n0);
-    q.j0 = j0; q.j1 = j1;
-    q.w0 = (float)(1.0 - w);
-    q.w1 = (float)w;
+    q.j[0] = j1; q.w[0] = (float)w;
+    q.j[1] = j0; q.w[1] = (float)(1.0 - w);
     return q;
 }
 
@@ -329,7 +387,7 @@ int check_hip(const char* what) {
 
 // ---- per-kernel timing ------------------------------------------------------
 const char* kKindNames[K_NUM_KINDS] = {"fill", "fwd_step", "rec_quant", "loss_final", "inject_shell",
-                                       "prim_rev", "adj_step", "scale_grad", "codec", "put"};
+                                       "prim_rev", "adj_step", "scale_grad", "codec", "put", "record"};
 constexpr size_t kMaxTimedLaunches = 1 << 16;
 
 struct Timing {
@@ -475,6 +533,16 @@ int forward_with(const Plan& pl, const fdtd_problem_t* prob, const fdtd_store_cf
                  float* fields, float* psi, void* store, char* ws, double* loss, double* loss_series,
                  fdtd_record_t* rec, hipStream_t s, bool allow_graph, const char* what) {
     Grid g = pl.g;
+    // the caller's workspace holds the class-sorted tile order; the library's own array
+    // (allow_graph false: no host allocation either) runs the tiles in x-y-z order
+    Tiling fwd = pl.fwd;
+    std::vector<int32_t> order;
+    if (allow_graph) {
+        tile_order(pl, 0, order);
+        fwd.order = (const int32_t*)(ws + pl.ws_order_fwd);
+    } else {
+        fwd.order = nullptr;
+    }
     g.coef = (const float*)(ws + pl.ws_coef);
     g.src_profile = (const float*)(ws + pl.ws_profile);
     g.msrc_profile = (const float*)(ws + pl.ws_mprofile);
@@ -492,15 +560,19 @@ int forward_with(const Plan& pl, const fdtd_problem_t* prob, const fdtd_store_cf
     auto mwave = [&](int n) { return pl.msrc_volume > 0 ? prob->msrc_wave[n] : 0.0f; };
     auto enqueue = [&](hipStream_t q) {
         put_tables(pl, prob, ws, q);
+        if (fwd.order) launch_put(ws + pl.ws_order_fwd, order.data(), (long long)order.size(), q);
         launch_fill(F[start], 6 * N, 0.0f, q);
         launch_fill(psi, 2 * (long long)pl.psi_floats, 0.0f, q);
         for (int n = 0; n < T; ++n) {
             const int slice = ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1;
             const float* in = F[(start + n) & 1];
             float* out = F[(start + n + 1) & 1];
-            launch_fwd_step(g, pl.fwd, in, out, psi, n & 1, eps, wave[n], mwave(n),
-                            partials + (int64_t)n * pl.per_step, store, staging, slice, q);
-            if (slice >= 0 && fp8) launch_rec_quant(g, staging, store, slice, q);
+            launch_fwd_step(g, fwd, in, out, psi, n & 1, eps, wave[n], mwave(n),
+                            partials + (int64_t)n * pl.per_step, q);
+            if (slice >= 0) {
+                launch_record(g, in, out, store, staging, slice, q);
+                if (fp8) launch_rec_quant(g, staging, store, slice, q);
+            }
         }
         launch_loss_final(partials, T, pl.per_step, loss, loss_series, q);
     };
@@ -581,24 +653,31 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
     g.src_profile = (const float*)(ws + pl.ws_profile);
     g.msrc_profile = (const float*)(ws + pl.ws_mprofile);
 
-    const int T = prob->steps, k = cfg->k;
+    const int T = prob->steps, k = cfg->k, ip = cfg->interp;
     const int64_t N = g.N;
     float* Fp[2] = {fields, (float*)(ws + pl.ws_fields)};                       // primal
     float* Fa[2] = {adj_fields, (float*)(ws + pl.ws_fields + pl.info.fields_bytes)};   // adjoint
     const float* wave = prob->src_wave;
     auto mwave = [&](int n) { return pl.msrc_volume > 0 ? prob->msrc_wave[n] : 0.0f; };
+    Tiling adj = pl.adj;
+    std::vector<int32_t> order_adj;
+    tile_order(pl, 1, order_adj);
+    adj.order = (const int32_t*)(ws + pl.ws_order_adj);
     auto enqueue = [&](hipStream_t q) {
         put_tables(pl, prob, ws, q);
+        launch_put(ws + pl.ws_order_adj, order_adj.data(), (long long)order_adj.size(), q);
         launch_fill(Fa[0], 6 * N, 0.0f, q);
         launch_fill(adj_psi, 2 * (long long)pl.psi_floats, 0.0f, q);
         launch_fill_f64(grad_eps, (long long)pl.info.design_cells, 0.0, q);
-        const Interp none{-1, 0, 0.0f, 0.0f};
+        Interp none;
+        for (int t = 0; t < 4; ++t) { none.j[t] = -1; none.w[t] = 0.0f; }
         // the interface shell of the output state of reverse step n (E^n high faces,
         // H^{n-1/2} low faces), written into buffer F before prim_rev of step n
         auto shell_for = [&](int n, float* F) {
-            return ShellJob{F, store, interp_for(n, T, k), n >= 1 ? interp_for(n - 1, T, k) : none, 1, n >= 1 ? 1 : 0};
+            return ShellJob{F, store, interp_for(n, T, k, ip), n >= 1 ? interp_for(n - 1, T, k, ip) : none, 1,
+                            n >= 1 ? 1 : 0};
         };
-        launch_inject_shell(g, ShellJob{Fp[0], store, none, interp_for(T - 1, T, k), 0, 1}, q);   // H^{T-1/2}
+        launch_inject_shell(g, ShellJob{Fp[0], store, none, interp_for(T - 1, T, k, ip), 0, 1}, q);   // H^{T-1/2}
         launch_inject_shell(g, shell_for(T - 1, Fp[1]), q);
         for (int n = T - 1; n >= 0; --n) {
             const int st = T - 1 - n;
@@ -611,7 +690,7 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
             launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], mwave(n), grad_eps, q);
             ShellJob next{};
             if (n >= 1) next = shell_for(n - 1, po);
-            launch_adj_step(g, pl.adj, ao, an, eps, adj_psi, st & 1, n >= 1 ? &next : nullptr, q);
+            launch_adj_step(g, adj, ao, an, eps, adj_psi, st & 1, n >= 1 ? &next : nullptr, q);
         }
         if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, q);
     };

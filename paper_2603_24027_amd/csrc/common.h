@@ -60,7 +60,6 @@ struct Grid {
     long long vps;           // values per kept step
     long long slice_stride;  // bytes between kept steps in the store
     long long scale_off;     // byte offset of the FP8 scale table in the store
-    uint32_t rec_off[12];    // element offset of each (face, component) block within a kept step
     // detector-loss partials (forward): blocks intersecting the detector
     int dbx0, dby0, dbz0, dnbx, dnby, dnbz;
 };
@@ -251,11 +250,37 @@ __host__ __device__ inline long long block_len(const Grid& g, int b) {
     return f == 0 ? (long long)g.my * g.mz : (f == 1 ? (long long)g.mx * g.mz : (long long)g.mx * g.my);
 }
 
-// Per-step parameters of the interpolating reinjection: v = w0 * slice(j0) + w1 * slice(j1);
-// j0 < 0 denotes the exact zero anchor before the first step.
+// Face cell t of the interface shell on the low (high = false) or high faces, with
+// t < my mz + mx mz + mx my (x face first, then y, then z): the cell (x, y, z), its
+// two tangential components (c0, c1), the first of its two blocks (blk) and its
+// position u within the block (block layouts as above).
+struct FaceCell {
+    int x, y, z, c0, c1, blk, u;
+};
+__device__ inline FaceCell face_cell(const Grid& g, int t, bool high) {
+    const int P = g.P;
+    const int ax = g.my * g.mz, ay = g.mx * g.mz;
+    const int b0 = high ? 6 : 0;
+    FaceCell f;
+    if (t < ax) {
+        f.u = t; f.blk = b0; f.y = P + f.u % g.my; f.z = P + f.u / g.my; f.x = high ? g.nx - P : P - 1;
+        f.c0 = 1; f.c1 = 2;
+    } else if (t < ax + ay) {
+        f.u = t - ax; f.blk = b0 + 2; f.x = P + f.u % g.mx; f.z = P + f.u / g.mx; f.y = high ? g.ny - P : P - 1;
+        f.c0 = 2; f.c1 = 0;
+    } else {
+        f.u = t - ax - ay; f.blk = b0 + 4; f.x = P + f.u % g.mx; f.y = P + f.u / g.mx; f.z = high ? g.nz - P : P - 1;
+        f.c0 = 0; f.c1 = 1;
+    }
+    return f;
+}
+
+// Per-step parameters of the interpolating reinjection: v = sum_t w[t] * slice(j[t]) over
+// the terms with j[t] >= 0 (j < 0: no term, or the exact zero anchor before the first
+// step); two terms for linear interpolation, four for the cubic option.
 struct Interp {
-    int j0, j1;
-    float w0, w1;
+    int j[4];
+    float w[4];
 };
 
 // The interface shell of one reverse step, to be written into the primal field
@@ -285,18 +310,15 @@ __device__ inline float load_code_t(const void* store, long long byte_slice, lon
     else return dec_f8<4, 3, 7, 1>(((const uint8_t*)base)[off]);
 }
 
-// Record one value of a kept step through a range-checked buffer store (dropped
-// when `on` is false): `r` covers the kept step's slice of the store, or for the
-// scaled FP8 type the FP32 staging buffer (quantised per block afterwards);
-// `elem` is the element index within it (block offset + position).
+// One recorded value at element `elem` of a kept step (block offset + position):
+// `dst` is the kept step's slice of the store, or for the scaled FP8 type the FP32
+// staging buffer (quantised per block afterwards).
 template <int DT>
-__device__ inline void record_b(__amdgpu_buffer_rsrc_t r, uint32_t elem, bool on, float v) {
-    const uint32_t oob = 0x80000000u;
+__device__ inline void store_code(void* __restrict__ dst, long long elem, float v) {
     if constexpr (DT == 0 || DT == 3) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, on ? elem * 4 : oob, 0, 0);
+        ((float*)dst)[elem] = v;
     } else if constexpr (DT == 1 || DT == 2) {
-        const uint16_t q = DT == 1 ? enc_fp16(v) : enc_bf16(v);
-        __builtin_amdgcn_raw_buffer_store_b16(q, r, on ? elem * 2 : oob, 0, 0);
+        ((uint16_t*)dst)[elem] = DT == 1 ? enc_fp16(v) : enc_bf16(v);
     } else {
         uint8_t q;
         if constexpr (DT == 4) q = enc_f8<4, 3, 11, 2>(v);
@@ -305,7 +327,7 @@ __device__ inline void record_b(__amdgpu_buffer_rsrc_t r, uint32_t elem, bool on
         else if constexpr (DT == 7) q = enc_f8<4, 3, 7, 0>(v);
         else if constexpr (DT == 8) q = enc_f8<3, 4, 3, 0>(v);
         else q = enc_f8<4, 3, 7, 1>(v);
-        __builtin_amdgcn_raw_buffer_store_b8(q, r, on ? elem : oob, 0, 0);
+        ((uint8_t*)dst)[elem] = q;
     }
 }
 
@@ -313,11 +335,13 @@ template <int DT>
 __device__ inline float shell_value_t(const Grid& g, const void* store, const Interp& q, int b, long long off) {
     const long long o = block_offset(g, b) + off;
     const float* scales = (const float*)((const char*)store + g.scale_off);
-    const float s1 = DT == 3 ? scales[q.j1 * 12 + b] : 1.0f;
-    float v = q.w1 * load_code_t<DT>(store, q.j1 * g.slice_stride, o, s1);
-    if (q.j0 >= 0) {
-        const float s0 = DT == 3 ? scales[q.j0 * 12 + b] : 1.0f;
-        v += q.w0 * load_code_t<DT>(store, q.j0 * g.slice_stride, o, s0);
+    float v = 0.0f;
+    #pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (q.j[t] >= 0) {
+            const float s = DT == 3 ? scales[q.j[t] * 12 + b] : 1.0f;
+            v += q.w[t] * load_code_t<DT>(store, q.j[t] * g.slice_stride, o, s);
+        }
     }
     return v;
 }
@@ -393,7 +417,7 @@ __device__ inline int slab_coord(int i, int n, int P) {   // -1 outside the slab
 // ----------------------------------------------------------------------------
 enum KernelKind {
     K_FILL = 0, K_FWD_STEP, K_REC_QUANT, K_LOSS_FINAL, K_INJECT, K_PRIM_REV, K_ADJ_STEP, K_SCALE_GRAD,
-    K_CODEC, K_PUT, K_NUM_KINDS
+    K_CODEC, K_PUT, K_RECORD, K_NUM_KINDS
 };
 
 // Defined in api.hip: hands out an event pair when timing is enabled.
@@ -409,14 +433,16 @@ inline void launch_kernel(int kind, Kernel kernel, dim3 grid, dim3 block, hipStr
 }
 
 // Launch wrappers (defined with the kernels)
-constexpr int PUT_CHUNK = 896;        // floats carried by one k_put launch (3.5 KB of arguments)
-void launch_put(float* dst, const float* host, long long n, hipStream_t s);
+constexpr int PUT_CHUNK = 896;        // 32-bit words carried by one k_put launch (3.5 KB of arguments)
+void launch_put(void* dst, const void* host, long long n, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 struct Tiling;
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                     const float* eps, float wave, float mwave, double* partials,
-                     void* store, float* staging, int slice, hipStream_t s);
+                     const float* eps, float wave, float mwave, double* partials, hipStream_t s);
+// recorder of kept step `slice` of forward step n (F0: its input E^n, F1: its output H^{n+1/2})
+void launch_record(const Grid& g, const float* F0, const float* F1, void* store, float* staging, int slice,
+                   hipStream_t s);
 // scaled FP8 recorder: the staging values of one kept step, then the chunk maxima
 long long rec_quant_scratch_floats(const Grid& g);
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s);

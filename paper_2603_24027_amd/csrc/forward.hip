@@ -33,24 +33,24 @@ __global__ void k_fill_f64(double* p, long long n, double v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
-// Host values written into device memory by kernel launches that carry them as
-// arguments (PUT_CHUNK floats per launch): no host staging buffer and no copy from
-// pageable memory, and a captured graph holds the values themselves.
+// Host values (32-bit words) written into device memory by kernel launches that carry
+// them as arguments (PUT_CHUNK words per launch): no host staging buffer and no copy
+// from pageable memory, and a captured graph holds the values themselves.
 struct PutChunk {
-    float v[PUT_CHUNK];
+    uint32_t v[PUT_CHUNK];
 };
 
-__global__ __launch_bounds__(256) void k_put(float* __restrict__ dst, int n, PutChunk c) {
+__global__ __launch_bounds__(256) void k_put(uint32_t* __restrict__ dst, int n, PutChunk c) {
     for (int i = threadIdx.x; i < n; i += 256) dst[i] = c.v[i];
 }
 
-void launch_put(float* dst, const float* host, long long n, hipStream_t s) {
+void launch_put(void* dst, const void* host, long long n, hipStream_t s) {
     for (long long o = 0; o < n; o += PUT_CHUNK) {
         const int m = (int)std::min<long long>(PUT_CHUNK, n - o);
         PutChunk c;
-        std::memcpy(c.v, host + o, (size_t)m * sizeof(float));
-        std::memset(c.v + m, 0, (size_t)(PUT_CHUNK - m) * sizeof(float));
-        launch_kernel(K_PUT, k_put, dim3(1), dim3(256), s, dst + o, m, c);
+        std::memcpy(c.v, (const uint32_t*)host + o, (size_t)m * sizeof(uint32_t));
+        std::memset(c.v + m, 0, (size_t)(PUT_CHUNK - m) * sizeof(uint32_t));
+        launch_kernel(K_PUT, k_put, dim3(1), dim3(256), s, (uint32_t*)dst + o, m, c);
     }
 }
 
@@ -85,7 +85,6 @@ __device__ inline void h_terms(const float (*cur)[TY + 2][EXT], const float (*nx
 // Buffer resources of one forward sweep.
 struct FwdBufs {
     rsrc_t F0, F1, psi, eps, src, msrc;              // fields in / out (E then H), both PML copies
-    rsrc_t rec;                                      // kept step: its store slice, or the FP32 staging
     uint32_t hin, hout;                              // byte offsets of the H-side PML copies in / out
 };
 
@@ -102,7 +101,7 @@ struct FwdLanes {
 // Everything the forward sweep reads from memory for plane k of its column:
 // E^n of plane k+1 (own cell and the LDS-ring position), H^{n-1/2} of plane k
 // (own cell and the halo cell), eps, the source profile (0 outside the source box)
-// and the PML auxiliaries of plane k.
+// and the PML auxiliaries of plane k (those of the axes the tile's class reaches).
 struct PlaneIn {
     float e1[3], er[3], h0[3], hh0[3], ep, sp;
     float ph[6], pe[6], phh[6];
@@ -115,7 +114,7 @@ __device__ __forceinline__ uint32_t src_plane(const Grid& g, int k, uint32_t lan
 }
 
 // Straight-line loads of plane k's inputs (out-of-domain and out-of-slab values read as 0).
-template <int TY, bool MS>
+template <int TY, int SL>
 __device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, const FwdLanes& L,
                                               const FwdCtx<TY>& c, int k, PlaneIn& d) {
     const uint32_t nb = (uint32_t)c.N << 2;
@@ -132,23 +131,23 @@ __device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, c
     const uint32_t vs = src_plane(g, k, L.src, ss);
     d.sp = bldv(b.src, vs, ss);
     const PsiPlane pH = psi_plane(g, 0, k, b.hin), pE = psi_plane(g, 1, k, 0);
-    bld_psi_v(b.psi, L.po, pH, d.ph);
-    bld_psi_v(b.psi, L.po, pE, d.pe);
-    bld_psi_v(b.psi, L.ph, pH, d.phh);
+    bld_psi_s<SL>(b.psi, L.po, pH, d.ph);
+    bld_psi_s<SL>(b.psi, L.po, pE, d.pe);
+    bld_psi_s<SL>(b.psi, L.ph, pH, d.phh);
 }
 
 // One plane k of the forward sweep: publish E^n(k+1) to LDS, H^{n+1/2}(k) on the own
 // and halo cells, then E^{n+1}(k) on the own cell.  `in` holds the plane's inputs,
 // loaded one plane ahead.  All stores are unconditional buffer stores (dropped for
-// idle lanes and cells outside a slab).
-template <int TY, int REC, int CZ, bool MS>
+// idle lanes and cells outside a slab).  SL: the tile's class (slab_class).
+template <int TY, int CZ, bool MS, int SL>
 __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const FwdLanes& L, const FwdCtx<TY>& c,
                                           float (*sE)[3][TY + 2][EXT], float (*sH)[TY + 1][TX + 1],
                                           const CoefTile<TY, CZ>& ct, int lz, int cur, int k,
                                           const PlaneIn& in, float eo[3], float& hx_prev, float& hy_prev, double& e2,
                                           float wave, float mwave) {
     const int nxt = 1 - cur;
-    const int P = c.P, x = c.x, y = c.y, row = c.row, lane = c.lane;
+    const int x = c.x, y = c.y, row = c.row, lane = c.lane;
     const uint32_t nb = (uint32_t)c.N << 2;
     const uint32_t sk = uni((uint32_t)(k * c.plane) << 2);
     const PsiPlane pH = psi_plane(g, 0, k, b.hout), pE = psi_plane(g, 1, k, 0);
@@ -178,9 +177,9 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
     {
         float t[6];
         h_terms<TY>(sE[cur], sE[nxt], lane + 1, row + 1, t);
-        cpml_x(cf_x(ct, 1, lane + 1), t, ph);
-        if (L.ysl) cpml_y(cf_y(ct, 1, row + 1), t, ph);
-        if (pH.zs) cpml_z(cf_z(ct, 1, lz), t, ph);
+        if constexpr ((SL & 1) != 0) cpml_x(cf_x(ct, 1, lane + 1), t, ph);
+        if constexpr ((SL & 2) != 0) { if (L.ysl) cpml_y(cf_y(ct, 1, row + 1), t, ph); }
+        if constexpr ((SL & 4) != 0) { if (pH.zs) cpml_z(cf_z(ct, 1, lz), t, ph); }
         const float dt = g.dt;
         const float m = MS ? dt * mwave * mp : 0.0f;     // magnetic current (0 outside its sheet)
         h[0] = c.live ? in.h0[0] - dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f) : 0.0f;
@@ -188,25 +187,7 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
         h[2] = c.live ? in.h0[2] - dt * (t[4] - t[5]) - (g.msrc_comp == 2 ? m : 0.0f) : 0.0f;
     }
     bst3v(b.F1, L.o, sk + 3 * nb, nb, h);
-    bst_psi_v(b.psi, L.po, pH, ph);
-    if constexpr (REC >= 0) {
-        // interface shell of a kept step: H^{n+1/2} on the low faces, E^n on the high faces;
-        // a cell lies on at most one face; the second component's block follows the first
-        const bool jI = y >= P && y < g.ny - P, kI = k >= P && k < g.nz - P, iI = x >= P && x < g.nx - P;
-        const uint32_t ax = (uint32_t)(g.my * g.mz), ay = (uint32_t)(g.mx * g.mz), az = (uint32_t)(g.mx * g.my);
-        uint32_t e = 0, ar = 0;
-        float v0 = 0.0f, v1 = 0.0f;
-        bool on = c.live;
-        if (x == P - 1 && jI && kI) { e = g.rec_off[0] + (k - P) * g.my + (y - P); ar = ax; v0 = h[1]; v1 = h[2]; }
-        else if (y == P - 1 && iI && kI) { e = g.rec_off[2] + (k - P) * g.mx + (x - P); ar = ay; v0 = h[2]; v1 = h[0]; }
-        else if (k == P - 1 && iI && jI) { e = g.rec_off[4] + (y - P) * g.mx + (x - P); ar = az; v0 = h[0]; v1 = h[1]; }
-        else if (x == g.nx - P && jI && kI) { e = g.rec_off[6] + (k - P) * g.my + (y - P); ar = ax; v0 = eo[1]; v1 = eo[2]; }
-        else if (y == g.ny - P && iI && kI) { e = g.rec_off[8] + (k - P) * g.mx + (x - P); ar = ay; v0 = eo[2]; v1 = eo[0]; }
-        else if (k == g.nz - P && iI && jI) { e = g.rec_off[10] + (y - P) * g.mx + (x - P); ar = az; v0 = eo[0]; v1 = eo[1]; }
-        else on = false;
-        record_b<REC>(b.rec, e, on, v0);
-        record_b<REC>(b.rec, e + ar, on, v1);
-    }
+    bst_psi_s<SL>(b.psi, L.po, pH, ph);
     sH[0][row + 1][lane + 1] = h[0];
     sH[1][row + 1][lane + 1] = h[1];
     sH[2][row + 1][lane + 1] = h[2];
@@ -215,7 +196,7 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
         if (c.hc.xy >= 0) {
             float t[6];
             h_terms<TY>(sE[cur], sE[nxt], c.hex, c.hey, t);
-            cpml_apply(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, lz), t, phh);
+            cpml_axes<SL>(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, lz), t, phh);
             const float dt = g.dt;
             const float m = MS ? dt * mwave * mph : 0.0f;
             hh[0] = in.hh0[0] - dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f);
@@ -235,10 +216,10 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
     t[3] = h[2] - sH[2][row + 1][lane];       // (Ey, x, -, Hz)
     t[4] = h[1] - sH[1][row + 1][lane];       // (Ez, x, +, Hy)
     t[5] = h[0] - sH[0][row][lane + 1];       // (Ez, y, -, Hx)
-    cpml_x(cf_x(ct, 0, lane + 1), t, pe);
-    if (L.ysl) cpml_y(cf_y(ct, 0, row + 1), t, pe);
-    if (pE.zs) cpml_z(cf_z(ct, 0, lz), t, pe);
-    bst_psi_v(b.psi, L.po, pE, pe);
+    if constexpr ((SL & 1) != 0) cpml_x(cf_x(ct, 0, lane + 1), t, pe);
+    if constexpr ((SL & 2) != 0) { if (L.ysl) cpml_y(cf_y(ct, 0, row + 1), t, pe); }
+    if constexpr ((SL & 4) != 0) { if (pE.zs) cpml_z(cf_z(ct, 0, lz), t, pe); }
+    bst_psi_s<SL>(b.psi, L.po, pE, pe);
     float u[3] = {t[0] - t[1], t[2] - t[3], t[4] - t[5]};
     const float jv = wave * in.sp;   // 0 outside the source box
     u[0] -= g.src_comp == 0 ? jv : 0.0f;
@@ -256,29 +237,96 @@ __device__ __forceinline__ void fwd_plane(const Grid& g, const FwdBufs& b, const
     eo[0] = in.e1[0]; eo[1] = in.e1[1]; eo[2] = in.e1[2];
 }
 
+// The z-march of one tile of class SL over planes [k0, k1): the prologue (E^n planes
+// k0-1 and k0 into LDS, H^{n+1/2} of the own column at k0-1, the inputs of plane k0),
+// then the planes, unrolled and software-pipelined: the loads of plane k+1 are issued
+// before the stores of plane k into the other of two register sets, so no wait for
+// them also waits for those stores (loads and stores retire in order).  Returns the
+// tile's detector term of this thread.
+template <int TY, int CZ, bool MS, int SL>
+__device__ __forceinline__ double fwd_tile(const Grid& g, const FwdBufs& b, const FwdLanes& Ln, const FwdCtx<TY>& c,
+                                           float (*sE)[3][TY + 2][EXT], float (*sH)[TY + 1][TX + 1],
+                                           const CoefTile<TY, CZ>& ct, int k0, int k1, float wave, float mwave) {
+    const int lane = c.lane, row = c.row, plane = c.plane;
+    const uint32_t nb = (uint32_t)c.N << 2;
+    PlaneIn pin[2];
+    float eo[3];                       // E^n of the own cell on the current plane
+    float hx_prev, hy_prev;            // H^{n+1/2} of the own cell on the previous plane
+    {
+        const int zm = bound(k0 - 1, g.nz, g.periodic);
+        const uint32_t sm = uni(zm < 0 ? 0u : (uint32_t)(zm * plane) << 2), s0 = uni((uint32_t)(k0 * plane) << 2);
+        float a[3], ra[3], rb[3], h0[3], p[6];
+        bld3v(b.F0, zm < 0 ? OOB : Ln.eo, sm, nb, a);
+        bld3v(b.F0, Ln.eo, s0, nb, eo);
+        bld3v(b.F0, zm < 0 ? OOB : Ln.er, sm, nb, ra);
+        bld3v(b.F0, Ln.er, s0, nb, rb);
+        const bool pro = c.live && zm >= 0;
+        bld3v(b.F0, zm < 0 ? OOB : Ln.o, sm + 3 * nb, nb, h0);
+        PsiPlane pm = psi_plane(g, 0, zm < 0 ? 0 : zm, b.hin);
+        pm.zs = pm.zs && zm >= 0;
+        PsiLane lm = Ln.po;
+        if (zm < 0) lm.x = lm.y = lm.z = OOB;
+        bld_psi_s<SL>(b.psi, lm, pm, p);
+        float mpm = 0.0f;
+        if constexpr (MS) {
+            uint32_t msm;
+            const bool mzm = zm >= 0 && box_plane(g.msrc_lo, g.msrc_hi, zm, msm);
+            mpm = bldv(b.msrc, mzm ? Ln.m : OOB, msm);
+        }
+        load_plane_in<TY, SL>(g, b, Ln, c, k0, pin[0]);
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            sE[0][q][row + 1][lane + 1] = a[q];
+            sE[1][q][row + 1][lane + 1] = eo[q];
+        }
+        if (c.rlx >= 0) {
+            #pragma unroll
+            for (int q = 0; q < 3; ++q) { sE[0][q][c.rly][c.rlx] = ra[q]; sE[1][q][c.rly][c.rlx] = rb[q]; }
+        }
+        __syncthreads();   // also publishes the coefficient tile
+        float t[6];
+        h_terms<TY>(sE[0], sE[1], lane + 1, row + 1, t);
+        cpml_axes<SL>(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), t, p);
+        const float m = g.dt * mwave * mpm;
+        hx_prev = pro ? h0[0] - g.dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f) : 0.0f;
+        hy_prev = pro ? h0[1] - g.dt * (t[2] - t[3]) - (g.msrc_comp == 1 ? m : 0.0f) : 0.0f;
+    }
+    __syncthreads();   // the first plane overwrites sE[0], which the prologue has just read
+    double e2 = 0.0;
+    #pragma unroll
+    for (int kk = 0; kk < CZ; ++kk) {
+        const int k = k0 + kk;
+        if (kk + 1 < CZ)   // inputs of the next plane (an unused valid plane past the end of the grid)
+            load_plane_in<TY, SL>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+        if (k < k1)
+            fwd_plane<TY, CZ, MS, SL>(g, b, Ln, c, sE, sH, ct, kk + 1, (kk + 1) & 1, k, pin[kk & 1], eo, hx_prev,
+                                      hy_prev, e2, wave, mwave);
+    }
+    return e2;
+}
+
 // One full forward step n: (E^n, H^{n-1/2}) in F0 -> (E^{n+1}, H^{n+1/2}) in F1 (each E
 // then H, 3 components of N cells).  The PML buffer holds two copies of the auxiliaries:
 // the H-side ones ping-pong (copy hcopy -> 1 - hcopy), the E-side ones live in copy 0
-// and are updated in place.
-// The z-march over CZ planes is unrolled and software-pipelined: the loads of plane
-// k+1 are issued before the stores of plane k into the other of two register sets,
-// so no wait for them also waits for those stores (loads and stores retire in order).
+// and are updated in place.  Each block runs the code of its tile's class: the PML
+// auxiliaries of an axis are loaded, updated and stored only by tiles that one of that
+// axis's slabs reaches (elsewhere they would all be out-of-range no-ops, and issuing
+// them had cost a third of the sweep's time).
 // With a magnetic-current sheet the sweep asks for 4 waves per SIMD: left free it
-// takes 132 vector registers (3 waves, 24 % slower); held to 128 it spills only
-// scalars, into vector-register lanes.
+// takes more than 128 vector registers (3 waves, 24 % slower); held to 128 it spills
+// only scalars, into vector-register lanes.
 #ifndef FDTD_FWD_WAVES
 #define FDTD_FWD_WAVES 1
 #endif
-template <int TY, int REC, int CZ, bool MS>
+template <int TY, int CZ, bool MS>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MS ? 4 : FDTD_FWD_WAVES))) void k_fwd_step(
     Grid g, Tiling tl, const float* __restrict__ F0, float* __restrict__ F1, float* __restrict__ psi, int hcopy,
-    const float* __restrict__ eps, float wave, float mwave, double* __restrict__ partials,
-    void* __restrict__ store, float* __restrict__ staging, int slice) {
+    const float* __restrict__ eps, float wave, float mwave, double* __restrict__ partials) {
     __shared__ float sE[2][3][TY + 2][EXT];
     __shared__ float sH[3][TY + 1][TX + 1];
     __shared__ CoefTile<TY, CZ> ct;
     __shared__ double red[TY];
-    const int L = logical_tile(tl.count);
+    const int L = logical_tile(tl);
     const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
     FwdCtx<TY> c;
     c.i0 = tix * TX;
@@ -294,8 +342,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MS ? 4 
     c.N = (int)g.N;
     c.P = g.P;
     c.plane = g.nx * g.ny;
-    const int N = c.N, plane = c.plane, lane = c.lane, row = c.row;
-    const uint32_t nb = (uint32_t)N << 2;
+    const int N = c.N, lane = c.lane, row = c.row;
     FwdBufs b;
     const uint32_t fbytes = (uint32_t)(6 * N) * 4u, psib = (uint32_t)g.psi_total * 4u;
     b.F0 = make_rsrc(F0, fbytes);
@@ -304,10 +351,6 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MS ? 4 
     b.hin = hcopy ? psib : 0u;
     b.hout = hcopy ? 0u : psib;
     b.eps = make_rsrc(eps, (uint32_t)(c.plane * g.nz) * 4u);
-    // a kept step records into its slice of the store (a store can exceed 4 GiB; one
-    // slice cannot), the scaled FP8 type into the FP32 staging buffer
-    if constexpr (REC == 3) b.rec = make_rsrc(staging, (uint32_t)g.vps * 4u);
-    else if constexpr (REC >= 0) b.rec = make_rsrc((char*)store + (long long)slice * g.slice_stride, (uint32_t)g.slice_stride);
     const int sxn = g.src_hi[0] - g.src_lo[0], syn = g.src_hi[1] - g.src_lo[1];
     b.src = make_rsrc(g.src_profile, (uint32_t)(sxn * syn * (g.src_hi[2] - g.src_lo[2])) * 4u);
     if constexpr (MS)
@@ -345,61 +388,19 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MS ? 4 
     Ln.ysl = c.own.sy >= 0;
     fill_coef_tile<TY, CZ>(g, ct, c.i0, c.j0, k0, c.tid, TX * TY);   // published by the prologue's barrier
 
-    // prologue: E^n planes k0-1 and k0 into LDS, H^{n+1/2} of this column at k0-1, and
-    // the inputs of plane k0
-    PlaneIn pin[2];
-    float eo[3];                       // E^n of the own cell on the current plane
-    float hx_prev, hy_prev;            // H^{n+1/2} of the own cell on the previous plane
-    {
-        const int zm = bound(k0 - 1, g.nz, g.periodic);
-        const uint32_t sm = uni(zm < 0 ? 0u : (uint32_t)(zm * plane) << 2), s0 = uni((uint32_t)(k0 * plane) << 2);
-        float a[3], ra[3], rb[3], h0[3], p[6];
-        bld3v(b.F0, zm < 0 ? OOB : Ln.eo, sm, nb, a);
-        bld3v(b.F0, Ln.eo, s0, nb, eo);
-        bld3v(b.F0, zm < 0 ? OOB : Ln.er, sm, nb, ra);
-        bld3v(b.F0, Ln.er, s0, nb, rb);
-        const bool pro = c.live && zm >= 0;
-        bld3v(b.F0, zm < 0 ? OOB : Ln.o, sm + 3 * nb, nb, h0);
-        PsiPlane pm = psi_plane(g, 0, zm < 0 ? 0 : zm, b.hin);
-        pm.zs = pm.zs && zm >= 0;
-        PsiLane lm = Ln.po;
-        if (zm < 0) lm.x = lm.y = lm.z = OOB;
-        bld_psi_v(b.psi, lm, pm, p);
-        float mpm = 0.0f;
-        if constexpr (MS) {
-            uint32_t msm;
-            const bool mzm = zm >= 0 && box_plane(g.msrc_lo, g.msrc_hi, zm, msm);
-            mpm = bldv(b.msrc, mzm ? Ln.m : OOB, msm);
-        }
-        load_plane_in<TY, MS>(g, b, Ln, c, k0, pin[0]);
-        #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            sE[0][q][row + 1][lane + 1] = a[q];
-            sE[1][q][row + 1][lane + 1] = eo[q];
-        }
-        if (c.rlx >= 0) {
-            #pragma unroll
-            for (int q = 0; q < 3; ++q) { sE[0][q][c.rly][c.rlx] = ra[q]; sE[1][q][c.rly][c.rlx] = rb[q]; }
-        }
-        __syncthreads();
-        float t[6];
-        h_terms<TY>(sE[0], sE[1], lane + 1, row + 1, t);
-        cpml_apply(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), t, p);
-        const float m = g.dt * mwave * mpm;
-        hx_prev = pro ? h0[0] - g.dt * (t[0] - t[1]) - (g.msrc_comp == 0 ? m : 0.0f) : 0.0f;
-        hy_prev = pro ? h0[1] - g.dt * (t[2] - t[3]) - (g.msrc_comp == 1 ? m : 0.0f) : 0.0f;
-    }
-    __syncthreads();   // the first plane overwrites sE[0], which the prologue has just read
-    double e2 = 0.0;
-    // REC: the storage type of this kept step, or -1 on a step that records nothing
-    #pragma unroll
-    for (int kk = 0; kk < CZ; ++kk) {
-        const int k = k0 + kk;
-        if (kk + 1 < CZ)   // inputs of the next plane (an unused valid plane past the end of the grid)
-            load_plane_in<TY, MS>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
-        if (k < k1)
-            fwd_plane<TY, REC, CZ, MS>(g, b, Ln, c, sE, sH, ct, kk + 1, (kk + 1) & 1, k, pin[kk & 1], eo, hx_prev,
-                                   hy_prev, e2, wave, mwave);
+    // the tile's class: the slabs that the cells it reads PML auxiliaries of reach
+    // (own and halo columns, planes k0-1 .. k0+CZ-1; uniform over the block)
+    const int sl = slab_class(g, c.i0 - 1, c.i0 + TX, c.j0 - 1, c.j0 + TY, k0 - 1, k0 + CZ);
+    double e2;
+    switch (sl) {
+        case 0: e2 = fwd_tile<TY, CZ, MS, 0>(g, b, Ln, c, sE, sH, ct, k0, k1, wave, mwave); break;
+        case 1: e2 = fwd_tile<TY, CZ, MS, 1>(g, b, Ln, c, sE, sH, ct, k0, k1, wave, mwave); break;
+        case 2: e2 = fwd_tile<TY, CZ, MS, 2>(g, b, Ln, c, sE, sH, ct, k0, k1, wave, mwave); break;
+        case 3: e2 = fwd_tile<TY, CZ, MS, 3>(g, b, Ln, c, sE, sH, ct, k0, k1, wave, mwave); break;
+        case 4: e2 = fwd_tile<TY, CZ, MS, 4>(g, b, Ln, c, sE, sH, ct, k0, k1, wave, mwave); break;
+        case 5: e2 = fwd_tile<TY, CZ, MS, 5>(g, b, Ln, c, sE, sH, ct, k0, k1, wave, mwave); break;
+        case 6: e2 = fwd_tile<TY, CZ, MS, 6>(g, b, Ln, c, sE, sH, ct, k0, k1, wave, mwave); break;
+        default: e2 = fwd_tile<TY, CZ, MS, 7>(g, b, Ln, c, sE, sH, ct, k0, k1, wave, mwave); break;
     }
     // detector partial of this tile (tiles intersecting the detector only; uniform per block)
     const int dx = tix - tl.dtx0, dy = tiy - tl.dty0, dz = tiz - tl.dtz0;
@@ -412,6 +413,29 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MS ? 4 
         for (int w = 0; w < TY; ++w) sum += red[w];
         partials[dx + (long long)tl.dntx * (dy + (long long)tl.dnty * dz)] = sum;
     }
+}
+
+// Recorder of one kept step (Section 2: the interface slices are recorded during the
+// forward simulation): the tangential H^{n+1/2} of the three low faces (index P-1),
+// from the step's output buffer F1, and the tangential E^n of the three high faces
+// (index n-P), from its input buffer F0, each over the interior extent of its face, as
+// the 12 blocks of kept step `slice`: encoded to the storage type, or (scaled FP8) in
+// FP32 into the staging buffer that the two quantisation launches then encode.  One
+// thread per face cell and side, both tangential components.
+template <int DT>
+__global__ __launch_bounds__(256) void k_record(Grid g, const float* __restrict__ F0, const float* __restrict__ F1,
+                                                void* __restrict__ dst) {
+    const int face = g.my * g.mz + g.mx * g.mz + g.mx * g.my;   // < 2^31: 24 N < 2^31
+    int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (t >= 2 * face) return;
+    const bool high = t >= face;
+    if (high) t -= face;
+    const FaceCell f = face_cell(g, t, high);
+    const long long N = g.N;
+    const float* A = high ? F0 : F1 + 3 * N;                   // E^n on the high faces, H^{n+1/2} on the low ones
+    const long long idx = f.x + (long long)g.nx * (f.y + (long long)g.ny * f.z);
+    store_code<DT>(dst, block_offset(g, f.blk) + f.u, A[f.c0 * N + idx]);
+    store_code<DT>(dst, block_offset(g, f.blk + 1) + f.u, A[f.c1 * N + idx]);
 }
 
 // FP8 recorder of one kept step, in two launches over (chunk, block) grids so that
@@ -479,43 +503,33 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
     if (threadIdx.x == 0) *loss = red[0];
 }
 
-template <int TY, int CZ, bool MS>
-static void launch_fwd_step_t(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                              const float* eps, float wave, float mwave, double* partials, void* store,
-                              float* staging, int slice, hipStream_t s) {
-    const dim3 grid(t.count), block(TX, TY);
-    if (slice < 0 || g.P == 0) {
-        launch_kernel(K_FWD_STEP, k_fwd_step<TY, -1, CZ, MS>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
-                      mwave, partials, store, staging, slice);
-        return;
-    }
-    with_dtype(g.dtype, [&]<int DT>() {
-        launch_kernel(K_FWD_STEP, k_fwd_step<TY, DT, CZ, MS>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
-                      mwave, partials, store, staging, slice);
-    });
-}
-
 template <int TY, int CZ>
-static void launch_fwd_step_m(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                              const float* eps, float wave, float mwave, double* partials, void* store,
-                              float* staging, int slice, hipStream_t s) {
+static void launch_fwd_step_t(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
+                              const float* eps, float wave, float mwave, double* partials, hipStream_t s) {
+    const dim3 grid(t.count), block(TX, TY);
     if (g.msrc_hi[0] > g.msrc_lo[0])
-        launch_fwd_step_t<TY, CZ, true>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
+        launch_kernel(K_FWD_STEP, k_fwd_step<TY, CZ, true>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
+                      mwave, partials);
     else
-        launch_fwd_step_t<TY, CZ, false>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
+        launch_kernel(K_FWD_STEP, k_fwd_step<TY, CZ, false>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
+                      mwave, partials);
 }
 
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                     const float* eps, float wave, float mwave, double* partials, void* store, float* staging,
-                     int slice, hipStream_t s) {
-    if (t.ty == 4 && t.cz == 4)
-        launch_fwd_step_m<4, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
-    else if (t.ty == 4)
-        launch_fwd_step_m<4, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
-    else if (t.cz == 4)
-        launch_fwd_step_m<8, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
-    else
-        launch_fwd_step_m<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, store, staging, slice, s);
+                     const float* eps, float wave, float mwave, double* partials, hipStream_t s) {
+    if (t.ty == 4 && t.cz == 4) launch_fwd_step_t<4, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, s);
+    else if (t.ty == 4) launch_fwd_step_t<4, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, s);
+    else if (t.cz == 4) launch_fwd_step_t<8, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, s);
+    else launch_fwd_step_t<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, s);
+}
+
+void launch_record(const Grid& g, const float* F0, const float* F1, void* store, float* staging, int slice,
+                   hipStream_t s) {
+    if (g.P == 0 || g.vps == 0) return;
+    const long long n = g.vps / 2;                      // face cells on both sides
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    void* dst = g.dtype == 3 ? (void*)staging : (void*)((char*)store + slice * g.slice_stride);
+    with_dtype(g.dtype, [&]<int DT>() { launch_kernel(K_RECORD, k_record<DT>, grid, block, s, g, F0, F1, dst); });
 }
 
 long long rec_quant_scratch_floats(const Grid& g) {

@@ -29,13 +29,21 @@ struct Tiling {
     int count;                // blocks
     // tiles intersecting the detector box (loss partials)
     int dtx0, dty0, dtz0, dntx, dnty, dntz;
+    // launch order of the tiles (count entries, device), or NULL for x-y-z order: tiles
+    // grouped by class, so that the blocks one compute unit runs at a time mostly share
+    // one of the class-specialised code paths (one path fills much of the instruction
+    // cache; blocks of several classes side by side had evicted each other's code)
+    const int32_t* order;
 };
 
-__device__ inline int logical_tile(int count) {
+// The tile of this block: workgroups go to the 8 XCDs round-robin, so position
+// (w & 7) * per + (w >> 3) gives each XCD one contiguous range of the order.
+__device__ inline int logical_tile(const Tiling& t) {
     const int w = blockIdx.x;
-    const int per = count >> 3;
+    const int per = t.count >> 3;
     const int full = per << 3;
-    return w < full ? (w & 7) * per + (w >> 3) : w;
+    const int p = w < full ? (w & 7) * per + (w >> 3) : w;
+    return t.order ? t.order[p] : p;
 }
 
 // Index along an axis after the boundary rule: -1 means "outside, value 0".
@@ -43,37 +51,6 @@ __device__ inline int bound(int x, int n, int periodic) {
     if (x >= 0 && x < n) return x;
     if (!periodic) return -1;
     return x < 0 ? x + n : x - n;
-}
-
-__device__ inline float ldg(const float* f, const Grid& g, int x, int y, int z) {
-    const int bx = bound(x, g.nx, g.periodic), by = bound(y, g.ny, g.periodic), bz = bound(z, g.nz, g.periodic);
-    if ((bx | by | bz) < 0) return 0.0f;
-    return f[bx + g.nx * (by + g.ny * bz)];
-}
-
-// Load plane z of the three components of a field into the extended LDS plane
-// s[c][ly][lx] (ly in [0, TY+2), lx in [0, EXT)), covering x in [i0-1, i0+TX],
-// y in [j0-1, j0+TY].  Every cell, inside the domain or not, receives the value
-// the boundary rule gives it.
-template <int TY>
-__device__ inline void load_ext_plane(float (*s)[TY + 2][EXT], const float* f, int N, const Grid& g,
-                                      int i0, int j0, int z) {
-    const int lane = threadIdx.x, ty = threadIdx.y;
-    #pragma unroll
-    for (int c = 0; c < 3; ++c) s[c][ty + 1][lane + 1] = ldg(f + c * N, g, i0 + lane, j0 + ty, z);
-    if (ty == 0) {
-        #pragma unroll
-        for (int c = 0; c < 3; ++c) s[c][0][lane + 1] = ldg(f + c * N, g, i0 + lane, j0 - 1, z);
-    } else if (ty == 1) {
-        #pragma unroll
-        for (int c = 0; c < 3; ++c) s[c][TY + 1][lane + 1] = ldg(f + c * N, g, i0 + lane, j0 + TY, z);
-    } else if (ty == 2 && lane < TY + 2) {
-        #pragma unroll
-        for (int c = 0; c < 3; ++c) s[c][lane][0] = ldg(f + c * N, g, i0 - 1, j0 - 1 + lane, z);
-    } else if (ty == 3 && lane < TY + 2) {
-        #pragma unroll
-        for (int c = 0; c < 3; ++c) s[c][lane][EXT - 1] = ldg(f + c * N, g, i0 + TX, j0 - 1 + lane, z);
-    }
 }
 
 // A column (x, y) of the grid after the boundary rule, with what a sweep needs
@@ -106,62 +83,6 @@ struct FwdCtx {
     int rlx, rly, hex, hey;
 };
 
-__device__ inline void load3(const float* __restrict__ f, int N, int idx, float v[3]) {
-    if (idx < 0) { v[0] = v[1] = v[2] = 0.0f; return; }
-    v[0] = f[idx];
-    v[1] = f[N + idx];
-    v[2] = f[2 * N + idx];
-}
-
-// Offsets of the two auxiliaries of each axis slab of a cell on plane z
-// (slab coordinate along z: sz): o[0] x-slab, o[1] y-slab, o[2] z-slab, -1 if
-// the cell is not in that slab.  side 0 = H-half arrays, 1 = E-half arrays.
-__device__ inline void psi_offsets(const Grid& g, const Col& c, int z, int sz, int side, int o[3]) {
-    const int P = g.P;
-    o[0] = c.sx >= 0 ? (int)(g.psi_off[0] + side * 2 * g.slab[0]) + c.sx + 2 * P * (c.y + g.ny * z) : -1;
-    o[1] = c.sy >= 0 ? (int)(g.psi_off[1] + side * 2 * g.slab[1]) + c.x + g.nx * (c.sy + 2 * P * z) : -1;
-    o[2] = (sz >= 0 && c.xy >= 0) ? (int)(g.psi_off[2] + side * 2 * g.slab[2]) + c.x + g.nx * (c.y + g.ny * sz) : -1;
-}
-
-// Auxiliaries of the six terms (x: 3, 4; y: 0, 5; z: 1, 2) at those offsets; 0 outside the slabs.
-__device__ inline void load_psi(const Grid& g, const float* __restrict__ psi, const int o[3], float p[6]) {
-    p[0] = p[1] = p[2] = p[3] = p[4] = p[5] = 0.0f;
-    if (o[0] >= 0) { p[3] = psi[o[0]]; p[4] = psi[o[0] + (int)g.slab[0]]; }
-    if (o[1] >= 0) { p[0] = psi[o[1]]; p[5] = psi[o[1] + (int)g.slab[1]]; }
-    if (o[2] >= 0) { p[1] = psi[o[2]]; p[2] = psi[o[2] + (int)g.slab[2]]; }
-}
-
-__device__ inline void store_psi(const Grid& g, float* __restrict__ psi, const int o[3], const float p[6]) {
-    if (o[0] >= 0) { psi[o[0]] = p[3]; psi[o[0] + (int)g.slab[0]] = p[4]; }
-    if (o[1] >= 0) { psi[o[1]] = p[0]; psi[o[1] + (int)g.slab[1]] = p[5]; }
-    if (o[2] >= 0) { psi[o[2]] = p[1]; psi[o[2] + (int)g.slab[2]] = p[2]; }
-}
-
-// CPML on the six differences t of one half step: inside the slab of a term's
-// axis, psi <- b psi + a t and t <- kinv t + psi (table: b | a | kinv, 2P each).
-__device__ inline void cpml_terms(const float* __restrict__ tab, int P, const Col& c, int sz, float t[6],
-                                  float p[6]) {
-    if (P == 0) return;
-    const float* b = tab;
-    const float* a = tab + 2 * P;
-    const float* kv = tab + 4 * P;
-    if (c.sx >= 0) {
-        const int s = c.sx;
-        p[3] = b[s] * p[3] + a[s] * t[3]; t[3] = kv[s] * t[3] + p[3];
-        p[4] = b[s] * p[4] + a[s] * t[4]; t[4] = kv[s] * t[4] + p[4];
-    }
-    if (c.sy >= 0) {
-        const int s = c.sy;
-        p[0] = b[s] * p[0] + a[s] * t[0]; t[0] = kv[s] * t[0] + p[0];
-        p[5] = b[s] * p[5] + a[s] * t[5]; t[5] = kv[s] * t[5] + p[5];
-    }
-    if (sz >= 0) {
-        const int s = sz;
-        p[1] = b[s] * p[1] + a[s] * t[1]; t[1] = kv[s] * t[1] + p[1];
-        p[2] = b[s] * p[2] + a[s] * t[2]; t[2] = kv[s] * t[2] + p[2];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Range-checked buffer access.  A load at an offset past the buffer returns 0
 // and a store there is dropped (raw buffer resource, stride 0), so a sweep can
@@ -184,42 +105,6 @@ constexpr uint32_t OOB = 0x80000000u;          // every buffer here is smaller t
 __device__ inline rsrc_t make_rsrc(const void* p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
-__device__ inline float bld(rsrc_t r, uint32_t off) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, FDTD_LD_AUX));
-}
-__device__ inline void bst(rsrc_t r, uint32_t off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, FDTD_ST_AUX);
-}
-// byte offset of element idx of component c of a 3-component field (OOB when idx < 0)
-__device__ inline uint32_t foff(int idx, int c, int N) {
-    return idx < 0 ? OOB : (uint32_t)(idx + c * N) << 2;
-}
-__device__ inline void bld3(rsrc_t r, int idx, int N, float v[3]) {
-    v[0] = bld(r, foff(idx, 0, N));
-    v[1] = bld(r, foff(idx, 1, N));
-    v[2] = bld(r, foff(idx, 2, N));
-}
-__device__ inline void bst3(rsrc_t r, int idx, int N, const float v[3]) {
-    bst(r, foff(idx, 0, N), v[0]);
-    bst(r, foff(idx, 1, N), v[1]);
-    bst(r, foff(idx, 2, N), v[2]);
-}
-// PML auxiliaries of the six terms at the offsets of psi_offsets (x: 3, 4; y: 0, 5; z: 1, 2)
-__device__ inline void bld_psi(const Grid& g, rsrc_t r, const int o[3], float p[6]) {
-    const uint32_t ox = o[0] < 0 ? OOB : (uint32_t)o[0] << 2, oy = o[1] < 0 ? OOB : (uint32_t)o[1] << 2;
-    const uint32_t oz = o[2] < 0 ? OOB : (uint32_t)o[2] << 2;
-    p[3] = bld(r, ox); p[4] = bld(r, ox == OOB ? OOB : ox + ((uint32_t)g.slab[0] << 2));
-    p[0] = bld(r, oy); p[5] = bld(r, oy == OOB ? OOB : oy + ((uint32_t)g.slab[1] << 2));
-    p[1] = bld(r, oz); p[2] = bld(r, oz == OOB ? OOB : oz + ((uint32_t)g.slab[2] << 2));
-}
-__device__ inline void bst_psi(const Grid& g, rsrc_t r, const int o[3], const float p[6]) {
-    const uint32_t ox = o[0] < 0 ? OOB : (uint32_t)o[0] << 2, oy = o[1] < 0 ? OOB : (uint32_t)o[1] << 2;
-    const uint32_t oz = o[2] < 0 ? OOB : (uint32_t)o[2] << 2;
-    bst(r, ox, p[3]); bst(r, ox == OOB ? OOB : ox + ((uint32_t)g.slab[0] << 2), p[4]);
-    bst(r, oy, p[0]); bst(r, oy == OOB ? OOB : oy + ((uint32_t)g.slab[1] << 2), p[5]);
-    bst(r, oz, p[1]); bst(r, oz == OOB ? OOB : oz + ((uint32_t)g.slab[2] << 2), p[2]);
-}
-
 // CPML coefficients of one axis at one position: psi <- b psi + a t, t <- kinv t + psi.
 // Outside the axis slab the triple is (0, 0, 1), which leaves t unchanged and psi 0,
 // so the update needs no branch.
@@ -274,16 +159,6 @@ __device__ inline Cf cf_y(const CoefTile<TY, CZ>& ct, int side, int ly) {
 template <int TY, int CZ>
 __device__ inline Cf cf_z(const CoefTile<TY, CZ>& ct, int side, int lz) {
     return Cf{ct.z[side][0][lz], ct.z[side][1][lz], ct.z[side][2][lz]};
-}
-
-// Branch-free CPML on the six differences t of one half step (x: 3, 4; y: 0, 5; z: 1, 2).
-__device__ inline void cpml_apply(const Cf& cx, const Cf& cy, const Cf& cz, float t[6], float p[6]) {
-    p[3] = cx.b * p[3] + cx.a * t[3]; t[3] = cx.k * t[3] + p[3];
-    p[4] = cx.b * p[4] + cx.a * t[4]; t[4] = cx.k * t[4] + p[4];
-    p[0] = cy.b * p[0] + cy.a * t[0]; t[0] = cy.k * t[0] + p[0];
-    p[5] = cy.b * p[5] + cy.a * t[5]; t[5] = cy.k * t[5] + p[5];
-    p[1] = cz.b * p[1] + cz.a * t[1]; t[1] = cz.k * t[1] + p[1];
-    p[2] = cz.b * p[2] + cz.a * t[2]; t[2] = cz.k * t[2] + p[2];
 }
 
 // Loads and stores addressed as a per-lane byte offset v (loop-invariant: the
@@ -357,21 +232,45 @@ __device__ inline PsiPlane psi_plane(const Grid& g, int side, int z, uint32_t ba
     p.dz = (uint32_t)g.slab[2] << 2;
     return p;
 }
-// the six auxiliaries (x: 3, 4; y: 0, 5; z: 1, 2); 0 outside the slabs
-__device__ inline void bld_psi_v(rsrc_t r, const PsiLane& l, const PsiPlane& p, float v[6]) {
-    const uint32_t vz = p.zs ? l.z : OOB;
-    v[3] = bldv(r, l.x, p.x); v[4] = bldv(r, l.x, p.x + p.dx);
-    v[0] = bldv(r, l.y, p.y); v[5] = bldv(r, l.y, p.y + p.dy);
-    v[1] = bldv(r, vz, p.z); v[2] = bldv(r, vz, p.z + p.dz);
+// The six auxiliaries (x: 3, 4; y: 0, 5; z: 1, 2) of the axes whose slabs a tile of
+// class SL (bit 0: x, 1: y, 2: z) reaches; out-of-slab cells read 0 and their stores are
+// dropped.  The other axes' auxiliaries are neither loaded nor stored (they would be
+// out of range for every cell of the tile) and read as 0.
+template <int SL>
+__device__ inline void bld_psi_s(rsrc_t r, const PsiLane& l, const PsiPlane& p, float v[6]) {
+    v[0] = v[1] = v[2] = v[3] = v[4] = v[5] = 0.0f;
+    if constexpr ((SL & 1) != 0) { v[3] = bldv(r, l.x, p.x); v[4] = bldv(r, l.x, p.x + p.dx); }
+    if constexpr ((SL & 2) != 0) { v[0] = bldv(r, l.y, p.y); v[5] = bldv(r, l.y, p.y + p.dy); }
+    if constexpr ((SL & 4) != 0) {
+        const uint32_t vz = p.zs ? l.z : OOB;
+        v[1] = bldv(r, vz, p.z); v[2] = bldv(r, vz, p.z + p.dz);
+    }
 }
-__device__ inline void bst_psi_v(rsrc_t r, const PsiLane& l, const PsiPlane& p, const float v[6]) {
-    const uint32_t vz = p.zs ? l.z : OOB;
-    bstv(r, l.x, p.x, v[3]); bstv(r, l.x, p.x + p.dx, v[4]);
-    bstv(r, l.y, p.y, v[0]); bstv(r, l.y, p.y + p.dy, v[5]);
-    bstv(r, vz, p.z, v[1]); bstv(r, vz, p.z + p.dz, v[2]);
+template <int SL>
+__device__ inline void bst_psi_s(rsrc_t r, const PsiLane& l, const PsiPlane& p, const float v[6]) {
+    if constexpr ((SL & 1) != 0) { bstv(r, l.x, p.x, v[3]); bstv(r, l.x, p.x + p.dx, v[4]); }
+    if constexpr ((SL & 2) != 0) { bstv(r, l.y, p.y, v[0]); bstv(r, l.y, p.y + p.dy, v[5]); }
+    if constexpr ((SL & 4) != 0) {
+        const uint32_t vz = p.zs ? l.z : OOB;
+        bstv(r, vz, p.z, v[1]); bstv(r, vz, p.z + p.dz, v[2]);
+    }
 }
 
-// CPML of one axis on its two terms (see cpml_apply); the y and z parts run under
+// Class of a tile: which axes' PML slabs (bit 0: x, 1: y, 2: z) reach the cells
+// [x0, x1] x [y0, y1] x [z0, z1] it touches (ranges clipped to the grid).  Outside a
+// slab of its axis the coefficients are (0, 0, 1), so skipping an axis that no cell of
+// the tile lies in changes no value.
+__host__ __device__ inline int slab_class(const Grid& g, int x0, int x1, int y0, int y1, int z0, int z1) {
+    if (g.P == 0) return 0;
+    auto reaches = [&](int lo, int hi, int n) {
+        lo = lo < 0 ? 0 : lo;
+        hi = hi > n - 1 ? n - 1 : hi;
+        return lo <= hi && (lo < g.P || hi >= n - g.P);
+    };
+    return (reaches(x0, x1, g.nx) ? 1 : 0) | (reaches(y0, y1, g.ny) ? 2 : 0) | (reaches(z0, z1, g.nz) ? 4 : 0);
+}
+
+// CPML of one axis on its two terms: psi <- b psi + a t, t <- kinv t + psi; the y and z parts run under
 // wave-uniform branches, the x part (which varies across a wave) always.
 __device__ inline void cpml_x(const Cf& c, float t[6], float p[6]) {
     p[3] = c.b * p[3] + c.a * t[3]; t[3] = c.k * t[3] + p[3];
@@ -384,6 +283,13 @@ __device__ inline void cpml_y(const Cf& c, float t[6], float p[6]) {
 __device__ inline void cpml_z(const Cf& c, float t[6], float p[6]) {
     p[1] = c.b * p[1] + c.a * t[1]; t[1] = c.k * t[1] + p[1];
     p[2] = c.b * p[2] + c.a * t[2]; t[2] = c.k * t[2] + p[2];
+}
+// CPML on the six differences t of one half step, on the axes of tile class SL
+template <int SL>
+__device__ inline void cpml_axes(const Cf& cx, const Cf& cy, const Cf& cz, float t[6], float p[6]) {
+    if constexpr ((SL & 1) != 0) cpml_x(cx, t, p);
+    if constexpr ((SL & 2) != 0) cpml_y(cy, t, p);
+    if constexpr ((SL & 4) != 0) cpml_z(cz, t, p);
 }
 
 }  // namespace fdtd

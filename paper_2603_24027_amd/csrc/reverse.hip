@@ -51,19 +51,28 @@ namespace fdtd {
 // adjoint sweep
 // --------------------------------------------------------------------------
 
-// Transpose of one half step's CPML at one cell.  o holds the six raw terms
-// (s * v_c for the E half, s * w_c for the H half; x: 3, 4; y: 0, 5; z: 1, 2);
-// inside the slab of a term's axis P = psibar + o, o <- kinv o + a P and the new
-// auxiliary is b P.  Outside a slab the coefficients (0, 0, 1) leave o unchanged.
-__device__ inline void gbar_apply(const Cf& cx, const Cf& cy, const Cf& cz, float o[6], const float pin[6],
-                                  float pout[6]) {
+// Transpose of one half step's CPML at one cell, on the axes of tile class SL.  o holds
+// the six raw terms (s * v_c for the E half, s * w_c for the H half; x: 3, 4; y: 0, 5;
+// z: 1, 2); inside the slab of a term's axis P = psibar + o, o <- kinv o + a P and the
+// new auxiliary is b P.  Outside a slab the coefficients (0, 0, 1) leave o unchanged;
+// the axes outside SL have them at every cell of the tile (new auxiliary 0, never stored).
+template <int SL>
+__device__ inline void gbar_axes(const Cf& cx, const Cf& cy, const Cf& cz, float o[6], const float pin[6],
+                                 float pout[6]) {
     float q;
-    q = pin[3] + o[3]; o[3] = cx.k * o[3] + cx.a * q; pout[3] = cx.b * q;
-    q = pin[4] + o[4]; o[4] = cx.k * o[4] + cx.a * q; pout[4] = cx.b * q;
-    q = pin[0] + o[0]; o[0] = cy.k * o[0] + cy.a * q; pout[0] = cy.b * q;
-    q = pin[5] + o[5]; o[5] = cy.k * o[5] + cy.a * q; pout[5] = cy.b * q;
-    q = pin[1] + o[1]; o[1] = cz.k * o[1] + cz.a * q; pout[1] = cz.b * q;
-    q = pin[2] + o[2]; o[2] = cz.k * o[2] + cz.a * q; pout[2] = cz.b * q;
+    pout[0] = pout[1] = pout[2] = pout[3] = pout[4] = pout[5] = 0.0f;
+    if constexpr ((SL & 1) != 0) {
+        q = pin[3] + o[3]; o[3] = cx.k * o[3] + cx.a * q; pout[3] = cx.b * q;
+        q = pin[4] + o[4]; o[4] = cx.k * o[4] + cx.a * q; pout[4] = cx.b * q;
+    }
+    if constexpr ((SL & 2) != 0) {
+        q = pin[0] + o[0]; o[0] = cy.k * o[0] + cy.a * q; pout[0] = cy.b * q;
+        q = pin[5] + o[5]; o[5] = cy.k * o[5] + cy.a * q; pout[5] = cy.b * q;
+    }
+    if constexpr ((SL & 4) != 0) {
+        q = pin[1] + o[1]; o[1] = cz.k * o[1] + cz.a * q; pout[1] = cz.b * q;
+        q = pin[2] + o[2]; o[2] = cz.k * o[2] + cz.a * q; pout[2] = cz.b * q;
+    }
 }
 
 // Hbar after the E-half transpose at the cell of extended coordinates (ex, ey):
@@ -102,6 +111,7 @@ struct AdjIn {
 };
 
 // Ebar, eps and E-side auxiliaries at the lane offsets (v, pl) on plane z (z < 0: 0, eps 1).
+template <int SL>
 __device__ __forceinline__ void load_ge_in(const Grid& g, const AdjBufs& b, uint32_t v, const PsiLane& pl, int z,
                                            int plane, uint32_t nb, float eb[3], float& ep, float pe[6]) {
     const uint32_t s = uni(z < 0 ? 0u : (uint32_t)(z * plane) << 2);
@@ -113,32 +123,34 @@ __device__ __forceinline__ void load_ge_in(const Grid& g, const AdjBufs& b, uint
     pp.zs = pp.zs && z >= 0;
     PsiLane l = pl;
     if (z < 0) l.x = l.y = l.z = OOB;
-    bld_psi_v(b.psi, l, pp, pe);
+    bld_psi_s<SL>(b.psi, l, pp, pe);
 }
 
-template <int TY>
+template <int TY, int SL>
 __device__ __forceinline__ void load_adj_in(const Grid& g, const AdjBufs& b, const AdjLanes& L, const FwdCtx<TY>& c,
                                             int k, AdjIn& d) {
     const uint32_t nb = (uint32_t)c.N << 2;
     const int z1 = bound(k + 1, g.nz, g.periodic);
-    load_ge_in(g, b, L.eo, L.pg, z1, c.plane, nb, d.eb, d.ep, d.pe);
-    load_ge_in(g, b, L.er, L.pr, z1, c.plane, nb, d.rb, d.rep, d.rpe);
+    load_ge_in<SL>(g, b, L.eo, L.pg, z1, c.plane, nb, d.eb, d.ep, d.pe);
+    load_ge_in<SL>(g, b, L.er, L.pr, z1, c.plane, nb, d.rb, d.rep, d.rpe);
     const uint32_t sk = uni(((uint32_t)(k * c.plane) << 2) + 3 * nb);
     bld3v(b.A0, L.o, sk, nb, d.hb);
     bld3v(b.A0, L.hc, sk, nb, d.hhb);
     const PsiPlane pH = psi_plane(g, 0, k, b.pin);
-    bld_psi_v(b.psi, L.po, pH, d.ph);
-    bld_psi_v(b.psi, L.ph, pH, d.phh);
+    bld_psi_s<SL>(b.psi, L.po, pH, d.ph);
+    bld_psi_s<SL>(b.psi, L.ph, pH, d.phh);
 }
 
 // E-half gbar at one position from its inputs: v = (dt/eps) Ebar, raw terms
-// (vx, -vx, vy, -vy, vz, -vz), CPML transpose; the new auxiliaries go to pout.
+// (vx, -vx, vy, -vy, vz, -vz), CPML transpose on the axes of class SL; the new
+// auxiliaries go to pout.
+template <int SL>
 __device__ __forceinline__ void ge_terms(float dt, const float eb[3], float ep, const float pe[6], const Cf& cx,
                                          const Cf& cy, const Cf& cz, float o[6], float pout[6]) {
     const float cc = dt_over_eps(dt, ep);
     const float vx = cc * eb[0], vy = cc * eb[1], vz = cc * eb[2];
     o[0] = vx; o[1] = -vx; o[2] = vy; o[3] = -vy; o[4] = vz; o[5] = -vz;
-    gbar_apply(cx, cy, cz, o, pe, pout);
+    gbar_axes<SL>(cx, cy, cz, o, pe, pout);
 }
 
 // Transpose of one axis' CPML on its two terms (x: 3, 4; y: 0, 5; z: 1, 2):
@@ -152,24 +164,25 @@ __device__ inline void gbar_axis(const Cf& c, int i, int j, float o[6], const fl
     pout[j] = c.b * q;
 }
 
-// E-half gbar of the own cell at plane k+1 (y and z parts under uniform branches).
-template <int TY, int CZ>
+// E-half gbar of the own cell at plane k+1 (y and z parts under uniform branches; the
+// axes outside class SL not at all).
+template <int TY, int CZ, int SL>
 __device__ __forceinline__ void ge_own(float dt, const CoefTile<TY, CZ>& ct, int lx, int ly, int lz, bool ysl,
                                        bool zsl, const float eb[3], float ep, const float pe[6], float o[6],
                                        float po[6]) {
     const float cc = dt_over_eps(dt, ep);
     const float vx = cc * eb[0], vy = cc * eb[1], vz = cc * eb[2];
     o[0] = vx; o[1] = -vx; o[2] = vy; o[3] = -vy; o[4] = vz; o[5] = -vz;
-    po[0] = po[1] = po[2] = po[5] = 0.0f;
-    gbar_axis(cf_x(ct, 0, lx), 3, 4, o, pe, po);
-    if (ysl) gbar_axis(cf_y(ct, 0, ly), 0, 5, o, pe, po);
-    if (zsl) gbar_axis(cf_z(ct, 0, lz), 1, 2, o, pe, po);
+    po[0] = po[1] = po[2] = po[3] = po[4] = po[5] = 0.0f;
+    if constexpr ((SL & 1) != 0) gbar_axis(cf_x(ct, 0, lx), 3, 4, o, pe, po);
+    if constexpr ((SL & 2) != 0) { if (ysl) gbar_axis(cf_y(ct, 0, ly), 0, 5, o, pe, po); }
+    if constexpr ((SL & 4) != 0) { if (zsl) gbar_axis(cf_z(ct, 0, lz), 1, 2, o, pe, po); }
 }
 
 // One plane k of the adjoint sweep: E-half gbar of plane k+1 (own cell and ring
 // position) into LDS, the H-half transpose on the own and halo cells of plane k,
 // then Ebar of the own cell at plane k.
-template <int TY, int CZ>
+template <int TY, int CZ, int SL>
 __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const AdjLanes& L, const FwdCtx<TY>& c,
                                           float (*sG)[6][TY + 2][EXT], float (*sGH)[TY + 1][TX + 1],
                                           const CoefTile<TY, CZ>& ct, int kk, int k, bool own_next, int cur,
@@ -184,14 +197,15 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
         PsiPlane pp = psi_plane(g, 1, z1 < 0 ? 0 : z1, b.pout);
         pp.zs = pp.zs && z1 >= 0;
         float o[6], po[6];
-        ge_own<TY, CZ>(dt, ct, lane + 1, row + 1, kk + 2, L.ysl, pp.zs, in.eb, in.ep, in.pe, o, po);
+        ge_own<TY, CZ, SL>(dt, ct, lane + 1, row + 1, kk + 2, L.ysl, pp.zs, in.eb, in.ep, in.pe, o, po);
         #pragma unroll
         for (int t = 0; t < 6; ++t) sG[nxt][t][row + 1][lane + 1] = o[t];
         PsiLane l = L.po;                        // the block's own cells at k+1 only
         if (!own_next || z1 < 0) l.x = l.y = l.z = OOB;
-        bst_psi_v(b.psi, l, pp, po);
+        bst_psi_s<SL>(b.psi, l, pp, po);
         if (c.rlx >= 0) {
-            ge_terms(dt, in.rb, in.rep, in.rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, kk + 2), o, po);
+            ge_terms<SL>(dt, in.rb, in.rep, in.rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, kk + 2), o,
+                         po);
             #pragma unroll
             for (int t = 0; t < 6; ++t) sG[nxt][t][c.rly][c.rlx] = o[t];
         }
@@ -207,11 +221,11 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
         bst3v(b.A1, L.o, sk + 3 * nb, nb, h);
         og[0] = -dt * h[0]; og[1] = dt * h[0]; og[2] = -dt * h[1]; og[3] = dt * h[1]; og[4] = -dt * h[2];
         og[5] = dt * h[2];
-        gbar_axis(cf_x(ct, 1, lane + 1), 3, 4, og, in.ph, po);
-        if (L.ysl) gbar_axis(cf_y(ct, 1, row + 1), 0, 5, og, in.ph, po);
-        if (pH.zs) gbar_axis(cf_z(ct, 1, kk + 1), 1, 2, og, in.ph, po);
+        if constexpr ((SL & 1) != 0) gbar_axis(cf_x(ct, 1, lane + 1), 3, 4, og, in.ph, po);
+        if constexpr ((SL & 2) != 0) { if (L.ysl) gbar_axis(cf_y(ct, 1, row + 1), 0, 5, og, in.ph, po); }
+        if constexpr ((SL & 4) != 0) { if (pH.zs) gbar_axis(cf_z(ct, 1, kk + 1), 1, 2, og, in.ph, po); }
         if (!c.live) og[0] = og[1] = og[2] = og[3] = og[4] = og[5] = 0.0f;
-        bst_psi_v(b.psi, L.po, pH, po);
+        bst_psi_s<SL>(b.psi, L.po, pH, po);
         #pragma unroll
         for (int t = 0; t < 6; ++t) sGH[t][row + 1][lane + 1] = og[t];
     }
@@ -222,7 +236,7 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
             hbar_new<TY>(sG[cur], sG[nxt], c.hex, c.hey, in.hhb, h);
             o[0] = -dt * h[0]; o[1] = dt * h[0]; o[2] = -dt * h[1]; o[3] = dt * h[1]; o[4] = -dt * h[2];
             o[5] = dt * h[2];
-            gbar_apply(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, kk + 1), o, in.phh, po);
+            gbar_axes<SL>(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, kk + 1), o, in.phh, po);
         }
         #pragma unroll
         for (int t = 0; t < 6; ++t) sGH[t][c.hey][c.hex] = o[t];
@@ -246,28 +260,17 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
 // the low faces.
 template <int DT>
 __device__ inline void shell_cell(const Grid& g, const ShellJob& j, int t) {
-    const int P = g.P;
-    const int ax = g.my * g.mz, ay = g.mx * g.mz, az = g.mx * g.my;   // face sizes (< 2^31: 24 N < 2^31)
-    const int face = ax + ay + az;
+    const int face = g.my * g.mz + g.mx * g.mz + g.mx * g.my;   // < 2^31: 24 N < 2^31
     const bool high = t >= face;
     if (high) t -= face;
     if (t >= face || (high ? !j.do_e : !j.do_h)) return;
-    const int N = (int)g.N;
-    float* A = j.F + (high ? 0 : 3 * (long long)N);         // E for the high faces, H for the low ones
+    const FaceCell f = face_cell(g, t, high);
+    const long long N = g.N;
+    float* A = j.F + (high ? 0 : 3 * N);                      // E for the high faces, H for the low ones
     const Interp& q = high ? j.qE : j.qH;
-    const int b0 = high ? 6 : 0;
-    int x, y, z, c0, c1, blk, u;
-    if (t < ax) {
-        u = t; blk = b0; y = P + u % g.my; z = P + u / g.my; x = high ? g.nx - P : P - 1; c0 = 1; c1 = 2;
-    } else if (t < ax + ay) {
-        u = t - ax; blk = b0 + 2; x = P + u % g.mx; z = P + u / g.mx; y = high ? g.ny - P : P - 1; c0 = 2; c1 = 0;
-    } else {
-        u = t - ax - ay; blk = b0 + 4; x = P + u % g.mx; y = P + u / g.mx; z = high ? g.nz - P : P - 1;
-        c0 = 0; c1 = 1;
-    }
-    const int idx = x + g.nx * (y + g.ny * z);
-    A[c0 * N + idx] = shell_value_t<DT>(g, j.store, q, blk, u);
-    A[c1 * N + idx] = shell_value_t<DT>(g, j.store, q, blk + 1, u);
+    const long long idx = f.x + (long long)g.nx * (f.y + (long long)g.ny * f.z);
+    A[f.c0 * N + idx] = shell_value_t<DT>(g, j.store, q, f.blk, f.u);
+    A[f.c1 * N + idx] = shell_value_t<DT>(g, j.store, q, f.blk + 1, f.u);
 }
 
 // the storage type is uniform over the launch: one branch per wave
@@ -291,10 +294,77 @@ __global__ __launch_bounds__(256) void k_inject_shell(Grid g, ShellJob j) {
     shell_cell<DT>(g, j, (int)blockIdx.x * 256 + (int)threadIdx.x);
 }
 
+// The z-march of one adjoint tile of class SL (slab_class) over planes [k0, k1).
+template <int TY, int CZ, int SL>
+__device__ __forceinline__ void adj_tile(const Grid& g, const AdjBufs& b, const AdjLanes& Ln, const FwdCtx<TY>& c,
+                                         float (*sG)[6][TY + 2][EXT], float (*sGH)[TY + 1][TX + 1],
+                                         const CoefTile<TY, CZ>& ct, int k0, int k1) {
+    const int lane = c.lane, row = c.row;
+    const uint32_t nb = (uint32_t)c.N << 2;
+    const float dt = g.dt;
+    // prologue: E-half gbar of planes k0-1 and k0, Ebar of the own cell at k0, and the
+    // z-terms of the H-half gbar of the own cell at k0-1
+    AdjIn pin[2];
+    float ebc[3];
+    float g1p, g2p;
+    {
+        const int zm = bound(k0 - 1, g.nz, g.periodic);
+        const int z0 = bound(k0, g.nz, g.periodic);
+        float eb[3], ep, pe[6], rb[3], rep, rpe[6], eb0[3], ep0, pe0[6], rb0[3], rep0, rpe0[6], hb[3], ph[6];
+        load_ge_in<SL>(g, b, Ln.eo, Ln.pg, zm, c.plane, nb, eb, ep, pe);
+        load_ge_in<SL>(g, b, Ln.er, Ln.pr, zm, c.plane, nb, rb, rep, rpe);
+        load_ge_in<SL>(g, b, Ln.eo, Ln.pg, z0, c.plane, nb, eb0, ep0, pe0);
+        load_ge_in<SL>(g, b, Ln.er, Ln.pr, z0, c.plane, nb, rb0, rep0, rpe0);
+        const bool pro = c.live && zm >= 0;
+        const uint32_t sm = uni(zm < 0 ? 0u : ((uint32_t)(zm * c.plane) << 2) + 3 * nb);
+        bld3v(b.A0, zm < 0 ? OOB : Ln.o, sm, nb, hb);
+        PsiPlane pm = psi_plane(g, 0, zm < 0 ? 0 : zm, b.pin);
+        pm.zs = pm.zs && zm >= 0;
+        PsiLane lm = Ln.po;
+        if (zm < 0) lm.x = lm.y = lm.z = OOB;
+        bld_psi_s<SL>(b.psi, lm, pm, ph);
+        load_adj_in<TY, SL>(g, b, Ln, c, k0, pin[0]);
+        float o[6], po[6];
+        ge_terms<SL>(dt, eb, ep, pe, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, 0), o, po);
+        #pragma unroll
+        for (int t = 0; t < 6; ++t) sG[0][t][row + 1][lane + 1] = o[t];
+        ge_terms<SL>(dt, eb0, ep0, pe0, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, 1), o, po);
+        #pragma unroll
+        for (int t = 0; t < 6; ++t) sG[1][t][row + 1][lane + 1] = o[t];
+        // the own cell's E-side auxiliaries at k0 belong to this block
+        bst_psi_s<SL>(b.psi, Ln.po, psi_plane(g, 1, z0, b.pout), po);
+        if (c.rlx >= 0) {
+            ge_terms<SL>(dt, rb, rep, rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, 0), o, po);
+            #pragma unroll
+            for (int t = 0; t < 6; ++t) sG[0][t][c.rly][c.rlx] = o[t];
+            ge_terms<SL>(dt, rb0, rep0, rpe0, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, 1), o, po);
+            #pragma unroll
+            for (int t = 0; t < 6; ++t) sG[1][t][c.rly][c.rlx] = o[t];
+        }
+        ebc[0] = eb0[0]; ebc[1] = eb0[1]; ebc[2] = eb0[2];
+        __syncthreads();
+        float h[3];
+        hbar_new<TY>(sG[0], sG[1], lane + 1, row + 1, hb, h);
+        o[0] = -dt * h[0]; o[1] = dt * h[0]; o[2] = -dt * h[1]; o[3] = dt * h[1]; o[4] = -dt * h[2]; o[5] = dt * h[2];
+        gbar_axes<SL>(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), o, ph, po);
+        g1p = pro ? o[1] : 0.0f;
+        g2p = pro ? o[2] : 0.0f;
+    }
+    __syncthreads();   // the first plane overwrites sG[0], which the prologue has just read
+    #pragma unroll
+    for (int kk = 0; kk < CZ; ++kk) {
+        const int k = k0 + kk;
+        if (kk + 1 < CZ) load_adj_in<TY, SL>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
+        if (k < k1)
+            adj_plane<TY, CZ, SL>(g, b, Ln, c, sG, sGH, ct, kk, k, k + 1 < k1, (kk + 1) & 1, pin[kk & 1], ebc, g1p, g2p);
+    }
+}
+
 // One adjoint step: (Ebar, Hbar) in A0 and the auxiliaries in PML copy `pcopy` ->
 // A1 and copy 1 - pcopy.  Ebar already carries this step's loss seed (added by the
 // primal reversal).  Unrolled over the CZ planes and software-pipelined like the
-// forward sweep.  Workgroups past the tile count write the shell `job`.
+// forward sweep; each block runs the code of its tile's class, as the forward sweep
+// does.  Workgroups past the tile count write the shell `job`.
 #ifndef FDTD_ADJ_WAVES
 #define FDTD_ADJ_WAVES 1
 #endif
@@ -309,7 +379,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
         shell_cell_any(g, job, ((int)blockIdx.x - tl.count) * (TX * TY) + (int)(threadIdx.y * TX + threadIdx.x));
         return;
     }
-    const int L = logical_tile(tl.count);
+    const int L = logical_tile(tl);
     const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
     FwdCtx<TY> c;
     c.i0 = tix * TX;
@@ -326,8 +396,6 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
     c.P = g.P;
     c.plane = g.nx * g.ny;
     const int lane = c.lane, row = c.row;
-    const uint32_t nb = (uint32_t)c.N << 2;
-    const float dt = g.dt;
     AdjBufs b;
     const uint32_t psib = (uint32_t)g.psi_total * 4u;
     b.A0 = make_rsrc(A0, (uint32_t)(6 * c.N) * 4u);
@@ -367,62 +435,17 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
     Ln.ysl = c.own.sy >= 0;
     fill_coef_tile<TY, CZ>(g, ct, c.i0, c.j0, k0, c.tid, TX * TY);
     __syncthreads();   // the prologue's E-half terms read the coefficient tile
-
-    // prologue: E-half gbar of planes k0-1 and k0, Ebar of the own cell at k0, and the
-    // z-terms of the H-half gbar of the own cell at k0-1
-    AdjIn pin[2];
-    float ebc[3];
-    float g1p, g2p;
-    {
-        const int zm = bound(k0 - 1, g.nz, g.periodic);
-        const int z0 = bound(k0, g.nz, g.periodic);
-        float eb[3], ep, pe[6], rb[3], rep, rpe[6], eb0[3], ep0, pe0[6], rb0[3], rep0, rpe0[6], hb[3], ph[6];
-        load_ge_in(g, b, Ln.eo, Ln.pg, zm, c.plane, nb, eb, ep, pe);
-        load_ge_in(g, b, Ln.er, Ln.pr, zm, c.plane, nb, rb, rep, rpe);
-        load_ge_in(g, b, Ln.eo, Ln.pg, z0, c.plane, nb, eb0, ep0, pe0);
-        load_ge_in(g, b, Ln.er, Ln.pr, z0, c.plane, nb, rb0, rep0, rpe0);
-        const bool pro = c.live && zm >= 0;
-        const uint32_t sm = uni(zm < 0 ? 0u : ((uint32_t)(zm * c.plane) << 2) + 3 * nb);
-        bld3v(b.A0, zm < 0 ? OOB : Ln.o, sm, nb, hb);
-        PsiPlane pm = psi_plane(g, 0, zm < 0 ? 0 : zm, b.pin);
-        pm.zs = pm.zs && zm >= 0;
-        PsiLane lm = Ln.po;
-        if (zm < 0) lm.x = lm.y = lm.z = OOB;
-        bld_psi_v(b.psi, lm, pm, ph);
-        load_adj_in<TY>(g, b, Ln, c, k0, pin[0]);
-        float o[6], po[6];
-        ge_terms(dt, eb, ep, pe, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, 0), o, po);
-        #pragma unroll
-        for (int t = 0; t < 6; ++t) sG[0][t][row + 1][lane + 1] = o[t];
-        ge_terms(dt, eb0, ep0, pe0, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, 1), o, po);
-        #pragma unroll
-        for (int t = 0; t < 6; ++t) sG[1][t][row + 1][lane + 1] = o[t];
-        // the own cell's E-side auxiliaries at k0 belong to this block
-        bst_psi_v(b.psi, Ln.po, psi_plane(g, 1, z0, b.pout), po);
-        if (c.rlx >= 0) {
-            ge_terms(dt, rb, rep, rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, 0), o, po);
-            #pragma unroll
-            for (int t = 0; t < 6; ++t) sG[0][t][c.rly][c.rlx] = o[t];
-            ge_terms(dt, rb0, rep0, rpe0, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, 1), o, po);
-            #pragma unroll
-            for (int t = 0; t < 6; ++t) sG[1][t][c.rly][c.rlx] = o[t];
-        }
-        ebc[0] = eb0[0]; ebc[1] = eb0[1]; ebc[2] = eb0[2];
-        __syncthreads();
-        float h[3];
-        hbar_new<TY>(sG[0], sG[1], lane + 1, row + 1, hb, h);
-        o[0] = -dt * h[0]; o[1] = dt * h[0]; o[2] = -dt * h[1]; o[3] = dt * h[1]; o[4] = -dt * h[2]; o[5] = dt * h[2];
-        gbar_apply(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), o, ph, po);
-        g1p = pro ? o[1] : 0.0f;
-        g2p = pro ? o[2] : 0.0f;
-    }
-    __syncthreads();   // the first plane overwrites sG[0], which the prologue has just read
-    #pragma unroll
-    for (int kk = 0; kk < CZ; ++kk) {
-        const int k = k0 + kk;
-        if (kk + 1 < CZ) load_adj_in<TY>(g, b, Ln, c, min(k + 1, g.nz - 1), pin[(kk + 1) & 1]);
-        if (k < k1)
-            adj_plane<TY, CZ>(g, b, Ln, c, sG, sGH, ct, kk, k, k + 1 < k1, (kk + 1) & 1, pin[kk & 1], ebc, g1p, g2p);
+    // the tile's class: the slabs that the cells it reads PML auxiliaries of reach
+    // (own, ring and halo columns, planes k0-1 .. k0+CZ; uniform over the block)
+    switch (slab_class(g, c.i0 - 1, c.i0 + TX, c.j0 - 1, c.j0 + TY, k0 - 1, k0 + CZ)) {
+        case 0: adj_tile<TY, CZ, 0>(g, b, Ln, c, sG, sGH, ct, k0, k1); break;
+        case 1: adj_tile<TY, CZ, 1>(g, b, Ln, c, sG, sGH, ct, k0, k1); break;
+        case 2: adj_tile<TY, CZ, 2>(g, b, Ln, c, sG, sGH, ct, k0, k1); break;
+        case 3: adj_tile<TY, CZ, 3>(g, b, Ln, c, sG, sGH, ct, k0, k1); break;
+        case 4: adj_tile<TY, CZ, 4>(g, b, Ln, c, sG, sGH, ct, k0, k1); break;
+        case 5: adj_tile<TY, CZ, 5>(g, b, Ln, c, sG, sGH, ct, k0, k1); break;
+        case 6: adj_tile<TY, CZ, 6>(g, b, Ln, c, sG, sGH, ct, k0, k1); break;
+        default: adj_tile<TY, CZ, 7>(g, b, Ln, c, sG, sGH, ct, k0, k1); break;
     }
 }
 
@@ -607,84 +630,17 @@ __device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const R
     }
 }
 
-// One reverse primal step over the box: (E^{n+1}, H^{n+1/2}) in F0 -> (E^n, H^{n-1/2})
-// in F1 on the interior, with the gradient and the loss seed.  The interface shell of
-// F1 (E^n on the high faces, H^{n-1/2} on the low faces) is written beforehand from the
-// store (by the previous adjoint launch, or k_inject_shell on the first reverse step);
-// the sweep reads the E part of it.
-#ifndef FDTD_REV_WAVES
-#define FDTD_REV_WAVES 1
-#endif
+// The z-march of one primal-reversal tile over planes [k0, k1).  (Tiles specialised by
+// what they need, as the forward and adjoint sweeps are, measured slower here: a launch
+// of this sweep is about one round of the chip, so blocks of every class run side by
+// side and their code paths evict each other from the instruction cache.)
 template <int TY, int CZ, bool MS>
-__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_REV_WAVES))) void k_prim_rev(
-    Grid g, Tiling tl, Box bx, const float* __restrict__ F0, float* __restrict__ F1, const float* __restrict__ eps,
-    float* __restrict__ Eb0, float wave, float mwave, double* __restrict__ grad) {
-    __shared__ float sH[2][3][TY + 2][EXT];       // H^{n+1/2}, extended planes
-    __shared__ float sE[2][3][TY + 1][TX + 1];     // E^n on the tile plus the +x column / +y row
-    const int L = logical_tile(tl.count);
-    const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
-    RevCtx<TY> c;
-    c.i0 = bx.tx0 + tix * TX;
-    c.j0 = bx.o[1] + tiy * TY;
-    const int k0 = bx.o[2] + tiz * CZ;
-    const int k1 = min(k0 + CZ, bx.o[2] + bx.n[2]);
-    c.lane = threadIdx.x;
-    c.row = threadIdx.y;
-    const int lane = c.lane, row = c.row;
-    c.x = c.i0 + lane;
-    c.y = c.j0 + row;
-    c.live = c.x >= bx.o[0] && c.x < bx.o[0] + bx.n[0] && c.y < bx.o[1] + bx.n[1];
-    c.N = (int)g.N;
-    c.plane = g.nx * g.ny;
-    const int N = c.N, P = g.P;
-    const uint32_t nb = (uint32_t)N << 2;
+__device__ __forceinline__ void rev_tile(const Grid& g, const RevBufs& b, const RevLanes& Ln, const RevCtx<TY>& c,
+                                         float (*sH)[3][TY + 2][EXT], float (*sE)[3][TY + 1][TX + 1], int k0, int k1,
+                                         float wave, float mwave, float* __restrict__ Eb0, double* __restrict__ grad) {
+    const int lane = c.lane, row = c.row, P = g.P;
+    const uint32_t nb = (uint32_t)c.N << 2;
     const float dt = g.dt;
-    RevBufs b;
-    b.F0 = make_rsrc(F0, (uint32_t)(6 * N) * 4u);
-    b.F1 = make_rsrc(F1, (uint32_t)(6 * N) * 4u);
-    b.eps = make_rsrc(eps, (uint32_t)(c.plane * g.nz) * 4u);
-    b.src = make_rsrc(g.src_profile, (uint32_t)((g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1]) *
-                                                (g.src_hi[2] - g.src_lo[2])) * 4u);
-    if constexpr (MS)
-        b.msrc = make_rsrc(g.msrc_profile, (uint32_t)((g.msrc_hi[0] - g.msrc_lo[0]) * (g.msrc_hi[1] - g.msrc_lo[1]) *
-                                                      (g.msrc_hi[2] - g.msrc_lo[2])) * 4u);
-    c.own = make_col(g, c.x, c.y);
-    c.rlx = c.rly = -1;
-    c.ring.xy = -1;
-    c.ring.x = c.ring.y = -1;
-    if (row == 0) { c.rlx = lane + 1; c.rly = 0; c.ring = make_col(g, c.i0 + lane, c.j0 - 1); }
-    else if (row == 1) { c.rlx = lane + 1; c.rly = TY + 1; c.ring = make_col(g, c.i0 + lane, c.j0 + TY); }
-    else if (row == 2 && lane < TY + 2) { c.rlx = 0; c.rly = lane; c.ring = make_col(g, c.i0 - 1, c.j0 - 1 + lane); }
-    else if (row == 3 && lane < TY + 2) { c.rlx = EXT - 1; c.rly = lane; c.ring = make_col(g, c.i0 + TX, c.j0 - 1 + lane); }
-    // extra E^n positions: the row y = j0+TY (wave 2) and the column x = i0+TX (wave 3),
-    // away from the ring rows of waves 0 and 1
-    c.pex = c.pey = -1;
-    c.xcol.xy = -1;
-    c.xcol.x = c.xcol.y = -1;
-    if (row == 2) { c.pex = lane; c.pey = TY; }
-    else if (row == 3 && lane < TY + 1) { c.pex = TX; c.pey = lane; }
-    if (c.pex >= 0) c.xcol = make_col(g, c.i0 + c.pex, c.j0 + c.pey);
-    RevLanes Ln;
-    // without wrap-around, idle lanes (outside the box) are never a neighbour of a box cell
-    Ln.h = lane_off(c.own.xy >= 0 && (c.live || g.periodic), c.own.xy);
-    Ln.r = lane_off(c.ring.xy >= 0, c.ring.xy);
-    Ln.e = lane_off(xy_interior(g, c.own), c.own.xy);
-    Ln.xe = lane_off(xy_interior(g, c.xcol), c.xcol.xy);
-    Ln.src = src_lane(g, c.own);
-    Ln.xsrc = src_lane(g, c.xcol);
-    Ln.st = lane_off(c.live && xy_interior(g, c.own), c.own.xy);
-    Ln.m = box_lane(g.msrc_lo, g.msrc_hi, c.own);
-    {
-        auto shell = [&](const Col& q, uint32_t& k_off, uint32_t& z_off) {
-            const bool iI = q.x >= P && q.x < g.nx - P, jI = q.y >= P && q.y < g.ny - P;
-            const bool fk = P > 0 && q.xy >= 0 && ((q.x == g.nx - P && jI) || (q.y == g.ny - P && iI));
-            k_off = lane_off(fk, q.xy);
-            z_off = lane_off(P > 0 && q.xy >= 0 && iI && jI, q.xy);
-        };
-        shell(c.own, Ln.shk, Ln.shz);
-        shell(c.xcol, Ln.xshk, Ln.xshz);
-    }
-
     // prologue: H^{n+1/2} planes k0-1 and k0 into LDS, then E^n at k0
     RevIn pin[2];
     {
@@ -757,6 +713,85 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
         }
         bst3v(b.F1, kI ? Ln.st : OOB, uni(((uint32_t)(k * c.plane) << 2) + 3 * nb), nb, h);
     }
+}
+
+// One reverse primal step over the box: (E^{n+1}, H^{n+1/2}) in F0 -> (E^n, H^{n-1/2})
+// in F1 on the interior, with the gradient and the loss seed.  The interface shell of
+// F1 (E^n on the high faces, H^{n-1/2} on the low faces) is written beforehand from the
+// store (by the previous adjoint launch, or k_inject_shell on the first reverse step);
+// the sweep reads the E part of it.
+#ifndef FDTD_REV_WAVES
+#define FDTD_REV_WAVES 1
+#endif
+template <int TY, int CZ, bool MS>
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_REV_WAVES))) void k_prim_rev(
+    Grid g, Tiling tl, Box bx, const float* __restrict__ F0, float* __restrict__ F1, const float* __restrict__ eps,
+    float* __restrict__ Eb0, float wave, float mwave, double* __restrict__ grad) {
+    __shared__ float sH[2][3][TY + 2][EXT];       // H^{n+1/2}, extended planes
+    __shared__ float sE[2][3][TY + 1][TX + 1];     // E^n on the tile plus the +x column / +y row
+    const int L = logical_tile(tl);
+    const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
+    RevCtx<TY> c;
+    c.i0 = bx.tx0 + tix * TX;
+    c.j0 = bx.o[1] + tiy * TY;
+    const int k0 = bx.o[2] + tiz * CZ;
+    const int k1 = min(k0 + CZ, bx.o[2] + bx.n[2]);
+    c.lane = threadIdx.x;
+    c.row = threadIdx.y;
+    const int lane = c.lane, row = c.row;
+    c.x = c.i0 + lane;
+    c.y = c.j0 + row;
+    c.live = c.x >= bx.o[0] && c.x < bx.o[0] + bx.n[0] && c.y < bx.o[1] + bx.n[1];
+    c.N = (int)g.N;
+    c.plane = g.nx * g.ny;
+    const int N = c.N, P = g.P;
+    RevBufs b;
+    b.F0 = make_rsrc(F0, (uint32_t)(6 * N) * 4u);
+    b.F1 = make_rsrc(F1, (uint32_t)(6 * N) * 4u);
+    b.eps = make_rsrc(eps, (uint32_t)(c.plane * g.nz) * 4u);
+    b.src = make_rsrc(g.src_profile, (uint32_t)((g.src_hi[0] - g.src_lo[0]) * (g.src_hi[1] - g.src_lo[1]) *
+                                                (g.src_hi[2] - g.src_lo[2])) * 4u);
+    if constexpr (MS)
+        b.msrc = make_rsrc(g.msrc_profile, (uint32_t)((g.msrc_hi[0] - g.msrc_lo[0]) * (g.msrc_hi[1] - g.msrc_lo[1]) *
+                                                      (g.msrc_hi[2] - g.msrc_lo[2])) * 4u);
+    c.own = make_col(g, c.x, c.y);
+    c.rlx = c.rly = -1;
+    c.ring.xy = -1;
+    c.ring.x = c.ring.y = -1;
+    if (row == 0) { c.rlx = lane + 1; c.rly = 0; c.ring = make_col(g, c.i0 + lane, c.j0 - 1); }
+    else if (row == 1) { c.rlx = lane + 1; c.rly = TY + 1; c.ring = make_col(g, c.i0 + lane, c.j0 + TY); }
+    else if (row == 2 && lane < TY + 2) { c.rlx = 0; c.rly = lane; c.ring = make_col(g, c.i0 - 1, c.j0 - 1 + lane); }
+    else if (row == 3 && lane < TY + 2) { c.rlx = EXT - 1; c.rly = lane; c.ring = make_col(g, c.i0 + TX, c.j0 - 1 + lane); }
+    // extra E^n positions: the row y = j0+TY (wave 2) and the column x = i0+TX (wave 3),
+    // away from the ring rows of waves 0 and 1
+    c.pex = c.pey = -1;
+    c.xcol.xy = -1;
+    c.xcol.x = c.xcol.y = -1;
+    if (row == 2) { c.pex = lane; c.pey = TY; }
+    else if (row == 3 && lane < TY + 1) { c.pex = TX; c.pey = lane; }
+    if (c.pex >= 0) c.xcol = make_col(g, c.i0 + c.pex, c.j0 + c.pey);
+    RevLanes Ln;
+    // without wrap-around, idle lanes (outside the box) are never a neighbour of a box cell
+    Ln.h = lane_off(c.own.xy >= 0 && (c.live || g.periodic), c.own.xy);
+    Ln.r = lane_off(c.ring.xy >= 0, c.ring.xy);
+    Ln.e = lane_off(xy_interior(g, c.own), c.own.xy);
+    Ln.xe = lane_off(xy_interior(g, c.xcol), c.xcol.xy);
+    Ln.src = src_lane(g, c.own);
+    Ln.xsrc = src_lane(g, c.xcol);
+    Ln.st = lane_off(c.live && xy_interior(g, c.own), c.own.xy);
+    Ln.m = box_lane(g.msrc_lo, g.msrc_hi, c.own);
+    {
+        auto shell = [&](const Col& q, uint32_t& k_off, uint32_t& z_off) {
+            const bool iI = q.x >= P && q.x < g.nx - P, jI = q.y >= P && q.y < g.ny - P;
+            const bool fk = P > 0 && q.xy >= 0 && ((q.x == g.nx - P && jI) || (q.y == g.ny - P && iI));
+            k_off = lane_off(fk, q.xy);
+            z_off = lane_off(P > 0 && q.xy >= 0 && iI && jI, q.xy);
+        };
+        shell(c.own, Ln.shk, Ln.shz);
+        shell(c.xcol, Ln.xshk, Ln.xshz);
+    }
+
+    rev_tile<TY, CZ, MS>(g, b, Ln, c, sH, sE, k0, k1, wave, mwave, Eb0, grad);
 }
 
 __global__ void k_scale_grad(double* g, long long n, const double* s) {

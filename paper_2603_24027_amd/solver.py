@@ -85,7 +85,7 @@ class Problem:
 
 def store_config(problem: Problem, dtype: str = "fp32", k: int = 1) -> FdtdStoreInfo:
     lib = load()
-    cfg = FdtdStoreCfg(STORE_DTYPES[dtype], int(k))
+    cfg = FdtdStoreCfg(STORE_DTYPES[dtype], int(k), _lib.INTERP_LINEAR)
     info = FdtdStoreInfo()
     check(lib.store_config(ctypes.byref(problem.c), ctypes.byref(cfg), ctypes.byref(info)))
     return info
@@ -112,16 +112,20 @@ class Gradient:
     """One problem + recorder configuration with its device buffers.
 
     forward(eps) records and returns the loss; backward() runs the time-reversed
-    pass and returns dL/deps on the design box (float64, [z][y][x]).
+    pass and returns dL/deps on the design box (float64, [z][y][x]).  interp picks
+    how the backward rebuilds the steps between kept ones: "linear" (the paper's)
+    or "cubic" (see include/fdtd.h).
     """
 
     def __init__(self, problem, dtype: str = "fp32", k: int = 1, device="cuda", series: bool = False,
-                 with_backward: bool = True):
+                 with_backward: bool = True, interp: str = "linear"):
         self.problem = problem if isinstance(problem, Problem) else Problem(problem)
         self.dtype = dtype
         self.k = int(k)
+        self.interp = interp
         self.device = torch.device(device)
-        self.cfg = FdtdStoreCfg(STORE_DTYPES[dtype], self.k)
+        self.cfg = FdtdStoreCfg(STORE_DTYPES[dtype], self.k,
+                                {"linear": _lib.INTERP_LINEAR, "cubic": _lib.INTERP_CUBIC}[interp])
         self.info = store_config(self.problem, dtype, k)
         i = self.info
         dev = self.device

@@ -15,9 +15,9 @@ def say(*a):
     print(*a, flush=True)
 
 
-def gpu_run(prob, dtype="fp32", k=1, series=False, backward=True, keep_fields=True):
+def gpu_run(prob, dtype="fp32", k=1, series=False, backward=True, keep_fields=True, interp="linear"):
     """Forward (+ backward) through the C ABI.  Returns dict with loss, series, E, H, grad, info."""
-    g = pk.Gradient(prob, dtype, k, device="cuda", series=series, with_backward=backward)
+    g = pk.Gradient(prob, dtype, k, device="cuda", series=series, with_backward=backward, interp=interp)
     eps = torch.from_numpy(np.ascontiguousarray(prob.eps, np.float32)).cuda()
     loss = g.forward(eps)
     out = {"info": g.info, "obj": g}

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_struct_layout_matches_header():
     # offsets of the ctypes mirror against the C layout rules for this header
-    assert ctypes.sizeof(_lib.FdtdStoreCfg) == 8
+    assert ctypes.sizeof(_lib.FdtdStoreCfg) == 12
     assert ctypes.sizeof(_lib.FdtdStoreInfo) == 11 * 8
     assert ctypes.sizeof(_lib.FdtdRecord) == 24
     assert _lib.FdtdProblem.courant.offset == 24
@@ -75,10 +75,10 @@ def test_compression_factor_64x_on_slab_config():
     assert full / small == 64.0
 
 
-def _call_forward(prob, dtype="fp32", k=1):
+def _call_forward(prob, dtype="fp32", k=1, interp=1):
     lib = pk.load()
     p = pk.Problem(prob)
-    cfg = _lib.FdtdStoreCfg(pk.STORE_DTYPES[dtype], k)
+    cfg = _lib.FdtdStoreCfg(pk.STORE_DTYPES[dtype], k, interp)
     rec = _lib.FdtdRecord()
     return lib.fdtd_forward(ctypes.byref(p.c), ctypes.byref(cfg), None, None, None, None, None, None, None,
                             ctypes.byref(rec), None)
@@ -103,6 +103,8 @@ def test_validation_errors_before_any_device_work():
     assert _call_forward(replace(pw, msrc_lo=(0, 3, 4))) == _lib.FDTD_EREGION   # sheet into the PML
     assert _call_forward(replace(pw, msrc_comp=3)) == _lib.FDTD_EINVAL
     assert _call_forward(base, k=0) == _lib.FDTD_ESTORE
+    assert _call_forward(base, interp=2) == _lib.FDTD_ESTORE               # only linear (0, 1) or cubic (3)
+    assert _call_forward(base, interp=3) == _lib.FDTD_EINVAL               # valid: fails on the NULL buffers
     assert _call_forward(base, dtype="fp8_e4m3_scaled", k=4) == _lib.FDTD_EINVAL
 
 

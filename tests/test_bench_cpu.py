@@ -88,7 +88,7 @@ def test_default_workload_is_hbm_bound_with_both_forms_and_a_crop():
     prob = w.make(bench.WORKLOADS[name][0])
     per_step = 52 * prob.cells            # both field buffers and eps touched by one forward step
     assert per_step > 1.5 * 256e6
-    assert bench.COMPRESSED[name][0] == ("fp8_e4m3_scaled", 16) and prob.steps % 16 == 0
+    assert bench.COMPRESSED[name][0] == ("fp8_e4m3_scaled", 16, "linear") and prob.steps % 16 == 0
     crop = w.make(bench.CROPS[name])
     assert crop.steps % 16 == 0 and crop.wavelength == prob.wavelength
     assert crop.design_shape == prob.design_shape and crop.pml == prob.pml

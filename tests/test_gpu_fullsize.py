@@ -203,22 +203,26 @@ def test_c2pw_fp32_gradient_matches_fp64_oracle():
 # At 77.5 cells (c4pcrop, ~136 steps per period, the paper's sampling) the bar is the
 # measured value rounded down: it is below the 0.999 target, which linear interpolation
 # at k = 16 does not reach.
-CROP_CASES = [("c5crop", "fp32", 1, 1 - 1e-9), ("c5crop", "bf16", 4, 0.999), ("c5crop", "fp8_e4m3_scaled", 16, 0.95),
-              ("c4crop", "fp32", 1, 1 - 1e-9), ("c4crop", "bf16", 4, 0.999), ("c4crop", "fp8_e4m3_scaled", 16, 0.9),
-              ("c4pcrop", "fp32", 1, 1 - 1e-9), ("c4pcrop", "fp8_e4m3_scaled", 8, 0.999),
-              ("c4pcrop", "fp8_e4m3_scaled", 16, 0.99)]
+# The cubic option (interp "cubic") rebuilds the skipped steps from four kept ones instead of two.
+CROP_CASES = [("c5crop", "fp32", 1, "linear", 1 - 1e-9), ("c5crop", "bf16", 4, "linear", 0.999),
+              ("c5crop", "fp8_e4m3_scaled", 16, "linear", 0.95),
+              ("c4crop", "fp32", 1, "linear", 1 - 1e-9), ("c4crop", "bf16", 4, "linear", 0.999),
+              ("c4crop", "fp8_e4m3_scaled", 16, "linear", 0.98), ("c4crop", "fp8_e4m3_scaled", 16, "cubic", 0.98),
+              ("c4pcrop", "fp32", 1, "linear", 1 - 1e-9), ("c4pcrop", "fp8_e4m3_scaled", 8, "linear", 0.9999),
+              ("c4pcrop", "fp8_e4m3_scaled", 16, "linear", 0.9985), ("c4pcrop", "fp8_e4m3_scaled", 16, "cubic", 0.999)]
 
 
-@pytest.mark.parametrize("preset,dtype,k,cos_min", CROP_CASES)
-def test_crop_gradient_vs_fp64_oracle(preset, dtype, k, cos_min):
+@pytest.mark.parametrize("preset,dtype,k,interp,cos_min", CROP_CASES)
+def test_crop_gradient_vs_fp64_oracle(preset, dtype, k, interp, cos_min):
     require_gpu()
     prob = w.make(preset, seed=0)
     exact = _oracle_gradient(prob.name, 0)
-    out = gpu_run(prob, dtype, k, keep_fields=False)
+    out = gpu_run(prob, dtype, k, keep_fields=False, interp=interp)
     g = out["grad"]
     r, c = metrics.rel_l2(g, exact), metrics.cosine_similarity(g, exact)
     ratio = 32 / pk.STORAGE_BITS[dtype] * k
-    say("%s %s k=%d (%.0fx smaller) vs FP64 oracle: cosine %.9f rel-L2 %.3e" % (preset, dtype, k, ratio, c, r))
+    say("%s %s k=%d %s (%.0fx smaller) vs FP64 oracle: cosine %.9f rel-L2 %.3e"
+        % (preset, dtype, k, interp, ratio, c, r))
     if k > 1:
         assert prob.steps % k == 0
         assert out["info"].payload_bytes * ratio == store_fp32_bytes(prob)

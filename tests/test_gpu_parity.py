@@ -192,6 +192,24 @@ def test_gradient_compressed_against_oracle_compressed(dtype, k):
         assert r <= 1e-3
 
 
+@pytest.mark.parametrize("dtype,k,case", [("fp32", 3, "c1"), ("fp32", 16, "c1"), ("fp8_e4m3_scaled", 16, "c1"),
+                                          ("bf16", 5, "ragged"), ("fp16", 4, "kappa")])
+def test_gradient_cubic_reconstruction_against_oracle(dtype, k, case):
+    """The cubic option of the reinjection (four nodes, zero anchor, shifted at the ends)
+    against the oracle running the same rule."""
+    require_gpu()
+    prob = CASES[case]()
+    say("gradient cubic", dtype, "k", k, case)
+    out = gpu_run(prob, dtype, k, interp="cubic")
+    _, g = adjoint.grad_time_reversal(prob, ORACLE_MODE[dtype], k, match_fp32=True, interp=3)
+    r = rel(out["grad"], g)
+    cos = metrics.cosine_similarity(out["grad"], g)
+    say("  vs oracle same codec and rule: rel-L2 %.3e cosine %.9f" % (r, cos))
+    assert cos >= 0.9999 and r <= 1e-2
+    if dtype == "fp32":
+        assert r <= 1e-3
+
+
 @pytest.mark.parametrize("dtype", ["fp8_e4m3b11fnuz", "fp8_e5m2fnuz", "fp8_e4m3fnuz", "fp8_e4m3", "fp8_e3m4",
                                    "fp8_e4m3fn"])
 def test_gradient_unscaled_fp8_against_oracle(dtype):
