@@ -672,24 +672,27 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
         Interp none;
         for (int t = 0; t < 4; ++t) { none.j[t] = -1; none.w[t] = 0.0f; }
         // the interface shell of the output state of reverse step n (E^n high faces,
-        // H^{n-1/2} low faces), written into buffer F before prim_rev of step n
-        auto shell_for = [&](int n, float* F) {
-            return ShellJob{F, store, interp_for(n, T, k, ip), n >= 1 ? interp_for(n - 1, T, k, ip) : none, 1,
+        // H^{n-1/2} low faces), written before prim_rev of step n: E into its input
+        // buffer FE (whose high-face E positions nothing else reads), H into its output
+        // buffer FH
+        auto shell_for = [&](int n, float* FE, float* FH) {
+            return ShellJob{FE, FH, store, interp_for(n, T, k, ip), n >= 1 ? interp_for(n - 1, T, k, ip) : none, 1,
                             n >= 1 ? 1 : 0};
         };
-        launch_inject_shell(g, ShellJob{Fp[0], store, none, interp_for(T - 1, T, k, ip), 0, 1}, q);   // H^{T-1/2}
-        launch_inject_shell(g, shell_for(T - 1, Fp[1]), q);
+        launch_inject_shell(g, ShellJob{Fp[0], Fp[0], store, none, interp_for(T - 1, T, k, ip), 0, 1}, q);   // H^{T-1/2}
+        launch_inject_shell(g, shell_for(T - 1, Fp[0], Fp[1]), q);
         for (int n = T - 1; n >= 0; --n) {
             const int st = T - 1 - n;
             float* po = Fp[st & 1];
             float* pn = Fp[(st + 1) & 1];
             float* ao = Fa[st & 1];
             float* an = Fa[(st + 1) & 1];
-            // the interior reversal reads the E part of pn's shell; the adjoint launch then
-            // writes the shell of step n-1 into po, which the reversal has finished reading
+            // the interior reversal reads the E part of the shell from po; the adjoint launch
+            // then writes the shell of step n-1: E into pn (which the reversal has just
+            // written: the input of step n-1), H into po (which it has finished reading)
             launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], mwave(n), grad_eps, q);
             ShellJob next{};
-            if (n >= 1) next = shell_for(n - 1, po);
+            if (n >= 1) next = shell_for(n - 1, pn, po);
             launch_adj_step(g, adj, ao, an, eps, adj_psi, st & 1, n >= 1 ? &next : nullptr, q);
         }
         if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, q);

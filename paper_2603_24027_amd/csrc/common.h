@@ -283,11 +283,12 @@ struct Interp {
     float w[4];
 };
 
-// The interface shell of one reverse step, to be written into the primal field
-// buffer F from the store: H at the low faces (interpolation qH) when do_h, E at
-// the high faces (interpolation qE) when do_e.
+// The interface shell of one reverse step, written from the store into primal field
+// buffers: E at the high faces (interpolation qE) into FE when do_e, H at the low
+// faces (interpolation qH) into FH when do_h.
 struct ShellJob {
-    float* F;
+    float* FE;
+    float* FH;
     const void* store;
     Interp qE, qH;
     int do_e, do_h;

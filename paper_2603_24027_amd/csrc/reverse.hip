@@ -33,9 +33,12 @@
 //
 // The interface shell that prim_rev of step n-1 needs (E^{n-1} on the high
 // faces, H^{n-3/2} on the low ones, decoded and interpolated from the store) is
-// written into the primal buffer that prim_rev of step n has just read, by
-// extra workgroups appended to the adjoint launch of step n, which touches
-// no primal buffer; only the first reverse step needs a launch of its own.
+// written by extra workgroups appended to the adjoint launch of step n, which
+// touches no primal buffer: E^{n-1} into the buffer prim_rev of step n has just
+// written (the input of step n-1, whose high-face E positions no sweep reads
+// otherwise, so that prim_rev reads E^{n} and the shell with one load), H^{n-3/2}
+// into the buffer prim_rev of step n has just read (the output of step n-1).  Only
+// the first reverse step needs a launch of its own.
 // Stores carry device scope (cache-policy bit sc1), as in the forward sweep: they
 // write through the XCD's L2 instead of leaving dirty lines for the writeback at
 // the end of every launch (measured: about 3 us of 64 per reverse step at 128^3).
@@ -266,7 +269,7 @@ __device__ inline void shell_cell(const Grid& g, const ShellJob& j, int t) {
     if (t >= face || (high ? !j.do_e : !j.do_h)) return;
     const FaceCell f = face_cell(g, t, high);
     const long long N = g.N;
-    float* A = j.F + (high ? 0 : 3 * N);                      // E for the high faces, H for the low ones
+    float* A = high ? j.FE : j.FH + 3 * N;                    // E for the high faces, H for the low ones
     const Interp& q = high ? j.qE : j.qH;
     const long long idx = f.x + (long long)g.nx * (f.y + (long long)g.ny * f.z);
     A[f.c0 * N + idx] = shell_value_t<DT>(g, j.store, q, f.blk, f.u);
@@ -467,18 +470,17 @@ struct RevBufs {
 // at plane k+1 (own cell and LDS-ring position), and E^{n+1}, eps and the source
 // profile at plane k+1 (own cell and the extra +x / +y position).
 struct RevIn {
-    float h[3], rh[3], e[3], xe[3], ep, xep, sp, xsp;
-    float sh[3], xsh[3];      // E^n of the high-face interface shell (0 elsewhere)
+    float h[3], rh[3], e[3], xe[3], ep, xep, sp, xsp;   // e, xe: E^{n+1}, or E^n on the high-face shell
     float mp;                 // magnetic-current profile of the own cell at plane k (0 off the sheet)
 };
 
 // Loop-invariant per-lane byte offsets: H of the own column and ring position
-// (boundary rule), E^{n+1}/eps of the own and extra positions where they are
-// interior in x and y, the source box column of both, the own cell's stores, and
-// the high-face shell cells of both positions (shk: on the x or y face, for
-// interior planes; shz: interior in x and y, for the z face plane).
+// (boundary rule), eps of the own and extra positions where they are interior in x
+// and y (e, xe: also the E loads of the z face plane nz-P, whose x-y interior is
+// shell), the E loads of interior planes (es, xes: interior in x and y, or on the
+// x or y high face), the source box column of both, and the own cell's stores.
 struct RevLanes {
-    uint32_t h, r, e, xe, src, xsrc, st, shk, shz, xshk, xshz, m;
+    uint32_t h, r, e, xe, es, xes, src, xsrc, st, m;
 };
 
 template <int TY>
@@ -513,8 +515,9 @@ __device__ __forceinline__ void load_rev_in(const Grid& g, const RevBufs& b, con
     bld3v(b.F0, z1 < 0 ? OOB : L.h, s1 + 3 * nb, nb, d.h);
     bld3v(b.F0, z1 < 0 ? OOB : L.r, s1 + 3 * nb, nb, d.rh);
     const bool zi = z1 >= 0 && z_interior(g, z1);
-    bld3v(b.F0, zi ? L.e : OOB, s1, nb, d.e);
-    bld3v(b.F0, zi ? L.xe : OOB, s1, nb, d.xe);
+    const bool zh = z1 >= 0 && g.P > 0 && z1 == g.nz - g.P;    // the z high face: shell
+    bld3v(b.F0, zi ? L.es : (zh ? L.e : OOB), s1, nb, d.e);
+    bld3v(b.F0, zi ? L.xes : (zh ? L.xe : OOB), s1, nb, d.xe);
     const float ep = bldv(b.eps, zi ? L.e : OOB, s1), xep = bldv(b.eps, zi ? L.xe : OOB, s1);
     d.ep = ep == 0.0f ? 1.0f : ep;      // positions that are not interior read 0
     d.xep = xep == 0.0f ? 1.0f : xep;
@@ -529,20 +532,16 @@ __device__ __forceinline__ void load_rev_in(const Grid& g, const RevBufs& b, con
     } else {
         d.mp = 0.0f;
     }
-    // the shell values were written into the output buffer before this sweep
-    const bool zh = z1 >= 0 && z1 == g.nz - g.P;
-    bld3v(b.F1, zi ? L.shk : (zh ? L.shz : OOB), s1, nb, d.sh);
-    bld3v(b.F1, zi ? L.xshk : (zh ? L.xshz : OOB), s1, nb, d.xsh);
 }
 
 // E^n at one position of plane z (column col, wrapped; extended-plane coordinates
 // (ex, ey) of the LDS H planes at z (hc) and z-1 (hp)).  Interior cells are
-// reversed, E^n = E^{n+1} - (dt/eps)(curl H - J); high-face shell cells take the
-// recorded values sh (0 for anything else).  u returns curl H - J (interior cells).
+// reversed, E^n = E^{n+1} - (dt/eps)(curl H - J); on high-face shell cells e1 is the
+// recorded E^n already, and anything else reads 0.  u returns curl H - J (interior cells).
 template <int TY>
 __device__ __forceinline__ void e_rev(const Grid& g, const float (*hc)[TY + 2][EXT], const float (*hp)[TY + 2][EXT],
                                       int ex, int ey, const Col& col, int z, const float e1[3], float ep, float sp,
-                                      const float sh[3], float wave, float e[3], float u[3], bool& interior) {
+                                      float wave, float e[3], float u[3], bool& interior) {
     const int P = g.P, x = col.x, y = col.y;
     const bool inside = col.xy >= 0 && z >= 0;
     const bool iI = x >= P && x < g.nx - P, jI = y >= P && y < g.ny - P, kI = z >= P && z < g.nz - P;
@@ -556,9 +555,9 @@ __device__ __forceinline__ void e_rev(const Grid& g, const float (*hc)[TY + 2][E
     u[1] -= g.src_comp == 1 ? jv : 0.0f;
     u[2] -= g.src_comp == 2 ? jv : 0.0f;
     const float cc = dt_over_eps(g.dt, ep);
-    e[0] = interior ? e1[0] - cc * u[0] : sh[0];
-    e[1] = interior ? e1[1] - cc * u[1] : sh[1];
-    e[2] = interior ? e1[2] - cc * u[2] : sh[2];
+    e[0] = interior ? e1[0] - cc * u[0] : e1[0];
+    e[1] = interior ? e1[1] - cc * u[1] : e1[1];
+    e[2] = interior ? e1[2] - cc * u[2] : e1[2];
 }
 
 // The owner of an interior cell on the design or detector box: this step's loss
@@ -604,13 +603,12 @@ template <int TY>
 __device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const RevLanes& L, const RevCtx<TY>& c,
                                         float (*sE)[TY + 1][TX + 1], const float (*hc)[TY + 2][EXT],
                                         const float (*hp)[TY + 2][EXT], int z, bool owned, const float e1[3], float ep,
-                                        float sp, const float sh[3], const float xe1[3], float xep, float xsp,
-                                        const float xsh[3], float wave, float* __restrict__ Eb0,
-                                        double* __restrict__ grad) {
+                                        float sp, const float xe1[3], float xep, float xsp, float wave,
+                                        float* __restrict__ Eb0, double* __restrict__ grad) {
     const int lane = c.lane, row = c.row;
     float e[3], u[3];
     bool interior;
-    e_rev<TY>(g, hc, hp, lane + 1, row + 1, c.own, z, e1, ep, sp, sh, wave, e, u, interior);
+    e_rev<TY>(g, hc, hp, lane + 1, row + 1, c.own, z, e1, ep, sp, wave, e, u, interior);
     sE[0][row][lane] = e[0];
     sE[1][row][lane] = e[1];
     sE[2][row][lane] = e[2];
@@ -623,7 +621,7 @@ __device__ __forceinline__ void e_plane(const Grid& g, const RevBufs& b, const R
         grad_and_seed(g, Eb0, grad, c.own.x, c.own.y, z, c.own.xy + z * c.plane, e1, h, ep, u);
     }
     if (c.pex >= 0) {
-        e_rev<TY>(g, hc, hp, c.pex + 1, c.pey + 1, c.xcol, z, xe1, xep, xsp, xsh, wave, e, u, interior);
+        e_rev<TY>(g, hc, hp, c.pex + 1, c.pey + 1, c.xcol, z, xe1, xep, xsp, wave, e, u, interior);
         sE[0][c.pey][c.pex] = e[0];
         sE[1][c.pey][c.pex] = e[1];
         sE[2][c.pey][c.pex] = e[2];
@@ -651,17 +649,13 @@ __device__ __forceinline__ void rev_tile(const Grid& g, const RevBufs& b, const 
         bld3v(b.F0, zm < 0 ? OOB : Ln.r, sm + 3 * nb, nb, rhm);
         bld3v(b.F0, Ln.h, s0 + 3 * nb, nb, h0);
         bld3v(b.F0, Ln.r, s0 + 3 * nb, nb, rh0);
-        const bool zi = z_interior(g, z0);
-        bld3v(b.F0, zi ? Ln.e : OOB, s0, nb, e1);
-        bld3v(b.F0, zi ? Ln.xe : OOB, s0, nb, xe1);
+        const bool zi = z_interior(g, z0), zh = P > 0 && z0 == g.nz - P;
+        bld3v(b.F0, zi ? Ln.es : (zh ? Ln.e : OOB), s0, nb, e1);
+        bld3v(b.F0, zi ? Ln.xes : (zh ? Ln.xe : OOB), s0, nb, xe1);
         float ep = bldv(b.eps, zi ? Ln.e : OOB, s0), xep = bldv(b.eps, zi ? Ln.xe : OOB, s0);
         uint32_t ss;
         const bool sz = src_z(g, z0, ss);
         const float sp = bldv(b.src, sz ? Ln.src : OOB, ss), xsp = bldv(b.src, sz ? Ln.xsrc : OOB, ss);
-        const bool zh = z0 == g.nz - P;
-        float sh[3], xsh[3];
-        bld3v(b.F1, zi ? Ln.shk : (zh ? Ln.shz : OOB), s0, nb, sh);
-        bld3v(b.F1, zi ? Ln.xshk : (zh ? Ln.xshz : OOB), s0, nb, xsh);
         load_rev_in<TY, MS>(g, b, Ln, c, k0, pin[0]);
         ep = ep == 0.0f ? 1.0f : ep;
         xep = xep == 0.0f ? 1.0f : xep;
@@ -675,7 +669,7 @@ __device__ __forceinline__ void rev_tile(const Grid& g, const RevBufs& b, const 
             for (int q = 0; q < 3; ++q) { sH[0][q][c.rly][c.rlx] = rhm[q]; sH[1][q][c.rly][c.rlx] = rh0[q]; }
         }
         __syncthreads();
-        e_plane<TY>(g, b, Ln, c, sE[0], sH[1], sH[0], z0, true, e1, ep, sp, sh, xe1, xep, xsp, xsh, wave, Eb0, grad);
+        e_plane<TY>(g, b, Ln, c, sE[0], sH[1], sH[0], z0, true, e1, ep, sp, xe1, xep, xsp, wave, Eb0, grad);
     }
     __syncthreads();   // the first plane overwrites sH[0], which the prologue has just read
     #pragma unroll
@@ -695,8 +689,8 @@ __device__ __forceinline__ void rev_tile(const Grid& g, const RevBufs& b, const 
         __syncthreads();
         // E^n at plane k+1 (own cell, and the +x column / +y row)
         const int z1 = bound(k + 1, g.nz, g.periodic);
-        e_plane<TY>(g, b, Ln, c, sE[en], sH[hn], sH[hc], z1, k + 1 < k1, in.e, in.ep, in.sp, in.sh, in.xe, in.xep,
-                    in.xsp, in.xsh, wave, Eb0, grad);
+        e_plane<TY>(g, b, Ln, c, sE[en], sH[hn], sH[hc], z1, k + 1 < k1, in.e, in.ep, in.sp, in.xe, in.xep, in.xsp,
+                    wave, Eb0, grad);
         __syncthreads();
         // H^{n-1/2} at plane k on the tile (interior cells; lane offset OOB elsewhere)
         const bool kI = z_interior(g, k);
@@ -717,9 +711,9 @@ __device__ __forceinline__ void rev_tile(const Grid& g, const RevBufs& b, const 
 
 // One reverse primal step over the box: (E^{n+1}, H^{n+1/2}) in F0 -> (E^n, H^{n-1/2})
 // in F1 on the interior, with the gradient and the loss seed.  The interface shell of
-// F1 (E^n on the high faces, H^{n-1/2} on the low faces) is written beforehand from the
-// store (by the previous adjoint launch, or k_inject_shell on the first reverse step);
-// the sweep reads the E part of it.
+// the step (E^n on the high faces, in F0; H^{n-1/2} on the low faces, in F1) is
+// written beforehand from the store (by the previous adjoint launch, or
+// k_inject_shell on the first reverse step); the sweep reads the E part of it.
 #ifndef FDTD_REV_WAVES
 #define FDTD_REV_WAVES 1
 #endif
@@ -781,14 +775,14 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     Ln.st = lane_off(c.live && xy_interior(g, c.own), c.own.xy);
     Ln.m = box_lane(g.msrc_lo, g.msrc_hi, c.own);
     {
-        auto shell = [&](const Col& q, uint32_t& k_off, uint32_t& z_off) {
+        // interior in x and y, or on the x or y high face (the E^n shell in the input buffer)
+        auto es = [&](const Col& q) {
             const bool iI = q.x >= P && q.x < g.nx - P, jI = q.y >= P && q.y < g.ny - P;
-            const bool fk = P > 0 && q.xy >= 0 && ((q.x == g.nx - P && jI) || (q.y == g.ny - P && iI));
-            k_off = lane_off(fk, q.xy);
-            z_off = lane_off(P > 0 && q.xy >= 0 && iI && jI, q.xy);
+            const bool face = P > 0 && ((q.x == g.nx - P && jI) || (q.y == g.ny - P && iI));
+            return lane_off(q.xy >= 0 && (xy_interior(g, q) || face), q.xy);
         };
-        shell(c.own, Ln.shk, Ln.shz);
-        shell(c.xcol, Ln.xshk, Ln.xshz);
+        Ln.es = es(c.own);
+        Ln.xes = es(c.xcol);
     }
 
     rev_tile<TY, CZ, MS>(g, b, Ln, c, sH, sE, k0, k1, wave, mwave, Eb0, grad);
