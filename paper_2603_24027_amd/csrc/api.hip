@@ -61,13 +61,16 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
 struct Plan {
     Grid g;
     Tiling fwd;            // forward sweep: the whole grid
+    Tiling fwd2;           // two-step forward sweep: the whole grid
+    int fwd_steps = 1;     // forward steps per sweep (1, or 2 where the two-step sweep applies)
     Tiling adj;            // adjoint sweep: the whole grid
     Tiling rev;            // primal reversal: the interior plus its shell
     int box_o[3], box_n[3];
     int rev_x0;                    // x origin of the primal-reversal tiles (128-byte aligned)
     fdtd_store_info_t info;
     uint64_t ws_coef = 0, ws_profile = 0, ws_partials = 0, ws_staging = 0, ws_fields = 0;
-    uint64_t ws_order_fwd = 0, ws_order_adj = 0;   // tile-order tables
+    uint64_t ws_order_fwd = 0, ws_order_adj = 0, ws_order_fwd2 = 0;   // tile-order tables
+    uint64_t ws_mid = 0;           // intermediate recorder values of a two-step sweep (one kept step, FP32)
     uint64_t psi_floats = 0;
     int per_step = 0;
     int64_t src_volume = 0;
@@ -207,6 +210,40 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     t.dtz0 = p->det_lo[2] / t.cz; t.dntz = (p->det_hi[2] - 1) / t.cz - t.dtz0 + 1;
     pl->per_step = t.dntx * t.dnty * t.dntz;
     t.order = nullptr;
+    {
+        // two forward steps per sweep: tiles of W2 columns, 12 rows, 16 (or 8) planes; not
+        // with a magnetic-current sheet (the single-step sweep carries it).  Measured at
+        // 512x512x256: 12x16 1620 us per launch, 12x8 1815, 8x16 1907 (8 rows: 146 registers,
+        // one 12-wave block per compute unit).
+        Tiling& t2 = pl->fwd2;
+        t2 = t;
+        t2.ty = 12;
+        t2.cz = env_int("FDTD_FWD2_TILE_Z", 16) == 8 ? 8 : 16;
+        t2.ntx = (p->nx + W2 - 1) / W2;
+        t2.nty = (p->ny + t2.ty - 1) / t2.ty;
+        t2.ntz = (p->nz + t2.cz - 1) / t2.cz;
+        t2.count = t2.ntx * t2.nty * t2.ntz;
+        t2.dtx0 = p->det_lo[0] / W2; t2.dntx = (p->det_hi[0] - 1) / W2 - t2.dtx0 + 1;
+        t2.dty0 = p->det_lo[1] / t2.ty; t2.dnty = (p->det_hi[1] - 1) / t2.ty - t2.dty0 + 1;
+        t2.dtz0 = p->det_lo[2] / t2.cz; t2.dntz = (p->det_hi[2] - 1) / t2.cz - t2.dtz0 + 1;
+        t2.order = nullptr;
+        // Two steps per sweep where at least half of the two-step tiles reach no PML slab.
+        // The sweep recomputes a two-cell halo (about 1.4x the arithmetic of two single
+        // steps), which the halved traffic pays for in interior tiles; tiles that carry
+        // PML auxiliaries cost about twice as much and hold the kernel's register budget.
+        // Measured: 512x512x256 (53 % interior tiles) forward 928 -> 810 us per step;
+        // 256x256x128 (39 %) 129.5 -> 136; 128^3 (none) 32.5 -> 55.
+        // FDTD_FWD_STEPS=1 or 2 overrides the choice.
+        int interior = 0;
+        for (int L = 0; L < t2.count; ++L) {
+            const int a = (L % t2.ntx) * W2, j0 = ((L / t2.ntx) % t2.nty) * t2.ty, k0 = (L / (t2.ntx * t2.nty)) * t2.cz;
+            if (slab_class(g, a - 2, a + TX - 3, j0 - 2, j0 + t2.ty + 1, k0 - 2, k0 + t2.cz) == 0) ++interior;
+        }
+        const int want = env_int("FDTD_FWD_STEPS", 0);
+        const bool two = want == 2 || (want != 1 && 2LL * interior >= t2.count);
+        pl->fwd_steps = (!has_m && two) ? 2 : 1;
+        if (pl->fwd_steps == 2) pl->per_step = std::max(pl->per_step, t2.dntx * t2.dnty * t2.dntz);
+    }
     for (int d = 0; d < 3; ++d) {
         pl->box_o[d] = P > 0 ? P - 1 : 0;
         pl->box_n[d] = P > 0 ? n[d] - 2 * P + 2 : n[d];
@@ -270,7 +307,9 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
         cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? align_up((uint64_t)rec_quant_scratch_floats(g) * 4, 256) : 0;
     pl->ws_order_fwd = pl->ws_staging + staging;
     pl->ws_order_adj = pl->ws_order_fwd + align_up(4ull * pl->fwd.count, 256);
-    pl->ws_fields = pl->ws_order_adj + align_up(4ull * pl->adj.count, 256);
+    pl->ws_order_fwd2 = pl->ws_order_adj + align_up(4ull * pl->adj.count, 256);
+    pl->ws_mid = pl->ws_order_fwd2 + (pl->fwd_steps == 2 ? align_up(4ull * pl->fwd2.count, 256) : 0);
+    pl->ws_fields = pl->ws_mid + (pl->fwd_steps == 2 ? align_up((uint64_t)g.vps * 4, 256) : 0);
     // second primal and second adjoint field buffers (ping-pong)
     in.workspace_bytes = pl->ws_fields + 2 * in.fields_bytes;
     in.design_cells = (uint64_t)(p->des_hi[0] - p->des_lo[0]) * (p->des_hi[1] - p->des_lo[1]) *
@@ -307,15 +346,22 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
 // all land on the first and last XCD), and within a chunk the tiles come class by class,
 // each class in x-y-z order (neighbouring tiles share halo lines in that XCD's L2, and
 // the blocks running side by side mostly share one class's code).
-// which: 0 forward, 1 adjoint.
+// which: 0 forward, 1 adjoint, 2 two-step forward.
 void tile_order(const Plan& pl, int which, std::vector<int32_t>& out) {
-    const Tiling& t = which == 0 ? pl.fwd : pl.adj;
+    const Tiling& t = which == 0 ? pl.fwd : (which == 1 ? pl.adj : pl.fwd2);
     std::vector<int32_t> cls((size_t)t.count);
     int counts[8] = {0};
     for (int L = 0; L < t.count; ++L) {
         const int tix = L % t.ntx, tiy = (L / t.ntx) % t.nty, tiz = L / (t.ntx * t.nty);
-        const int i0 = tix * TX, j0 = tiy * t.ty, k0 = tiz * t.cz;
-        const int c = slab_class(pl.g, i0 - 1, i0 + TX, j0 - 1, j0 + t.ty, k0 - 1, k0 + t.cz);
+        const int j0 = tiy * t.ty, k0 = tiz * t.cz;
+        int c;
+        if (which == 2) {
+            const int a = tix * W2;   // the two-step tile reads two cells around its own
+            c = slab_class(pl.g, a - 2, a + TX - 3, j0 - 2, j0 + t.ty + 1, k0 - 2, k0 + t.cz);
+        } else {
+            const int i0 = tix * TX;
+            c = slab_class(pl.g, i0 - 1, i0 + TX, j0 - 1, j0 + t.ty, k0 - 1, k0 + t.cz);
+        }
         cls[(size_t)L] = c;
         ++counts[c];
     }
@@ -387,7 +433,7 @@ int check_hip(const char* what) {
 
 // ---- per-kernel timing ------------------------------------------------------
 const char* kKindNames[K_NUM_KINDS] = {"fill", "fwd_step", "rec_quant", "loss_final", "inject_shell",
-                                       "prim_rev", "adj_step", "scale_grad", "codec", "put", "record"};
+                                       "prim_rev", "adj_step", "scale_grad", "codec", "put", "record", "fwd2_step"};
 constexpr size_t kMaxTimedLaunches = 1 << 16;
 
 struct Timing {
@@ -500,7 +546,8 @@ uint64_t call_key(const Plan& pl, int dir, const fdtd_store_cfg_t* cfg, std::ini
     uint64_t h = fnv1a(pl.hash, &dir, sizeof dir);
     h = fnv1a(h, cfg, sizeof *cfg);
     // the tile shapes (they can be changed between calls through the environment)
-    const int tiles[6] = {pl.fwd.ty, pl.fwd.cz, pl.adj.ty, pl.adj.cz, pl.rev.ty, pl.rev.cz};
+    const int tiles[9] = {pl.fwd.ty, pl.fwd.cz, pl.adj.ty, pl.adj.cz, pl.rev.ty, pl.rev.cz,
+                          pl.fwd2.ty, pl.fwd2.cz, pl.fwd_steps};
     h = fnv1a(h, tiles, sizeof tiles);
     for (const void* p : ptrs) h = fnv1a(h, &p, sizeof p);
     return h;
@@ -535,13 +582,17 @@ int forward_with(const Plan& pl, const fdtd_problem_t* prob, const fdtd_store_cf
     Grid g = pl.g;
     // the caller's workspace holds the class-sorted tile order; the library's own array
     // (allow_graph false: no host allocation either) runs the tiles in x-y-z order
-    Tiling fwd = pl.fwd;
-    std::vector<int32_t> order;
+    Tiling fwd = pl.fwd, fwd2 = pl.fwd2;
+    const bool two = pl.fwd_steps == 2;
+    std::vector<int32_t> order, order2;
+    fwd.order = fwd2.order = nullptr;
     if (allow_graph) {
         tile_order(pl, 0, order);
         fwd.order = (const int32_t*)(ws + pl.ws_order_fwd);
-    } else {
-        fwd.order = nullptr;
+        if (two) {
+            tile_order(pl, 2, order2);
+            fwd2.order = (const int32_t*)(ws + pl.ws_order_fwd2);
+        }
     }
     g.coef = (const float*)(ws + pl.ws_coef);
     g.src_profile = (const float*)(ws + pl.ws_profile);
@@ -551,28 +602,51 @@ int forward_with(const Plan& pl, const fdtd_problem_t* prob, const fdtd_store_cf
 
     const int64_t N = g.N;
     const int T = prob->steps, k = cfg->k;
-    // ping-pong field buffers; the parity of T picks the start so that the
-    // final state lands in the caller's buffer
+    // Sweeps: one step per sweep, or (two-step mode) a single step first when T is odd,
+    // then pairs.  Ping-pong field buffers; the parity of the sweep count picks the start
+    // so that the final state lands in the caller's buffer.
+    const int single = two ? (T & 1) : T;
+    const int sweeps = two ? single + T / 2 : T;
     float* F[2] = {fields, (float*)(ws + pl.ws_fields)};
-    const int start = T & 1;
+    const int start = sweeps & 1;
     const bool fp8 = cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED && g.vps > 0;
     const float* wave = prob->src_wave;
+    float* mid = two ? (float*)(ws + pl.ws_mid) : nullptr;
     auto mwave = [&](int n) { return pl.msrc_volume > 0 ? prob->msrc_wave[n] : 0.0f; };
+    auto slice_of = [&](int n) { return ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1; };
+    auto record = [&](const float* E, bool e_mid, const float* H, bool h_mid, int slice, hipStream_t q) {
+        launch_record(g, E, e_mid, H, h_mid, store, staging, slice, q);
+        if (fp8) launch_rec_quant(g, staging, store, slice, q);
+    };
     auto enqueue = [&](hipStream_t q) {
         put_tables(pl, prob, ws, q);
         if (fwd.order) launch_put(ws + pl.ws_order_fwd, order.data(), (long long)order.size(), q);
+        if (fwd2.order) launch_put(ws + pl.ws_order_fwd2, order2.data(), (long long)order2.size(), q);
         launch_fill(F[start], 6 * N, 0.0f, q);
         launch_fill(psi, 2 * (long long)pl.psi_floats, 0.0f, q);
-        for (int n = 0; n < T; ++n) {
-            const int slice = ((T - 1 - n) % k == 0) ? (T - 1 - n) / k : -1;
-            const float* in = F[(start + n) & 1];
-            float* out = F[(start + n + 1) & 1];
-            launch_fwd_step(g, fwd, in, out, psi, n & 1, eps, wave[n], mwave(n),
-                            partials + (int64_t)n * pl.per_step, q);
-            if (slice >= 0) {
-                launch_record(g, in, out, store, staging, slice, q);
-                if (fp8) launch_rec_quant(g, staging, store, slice, q);
-            }
+        // the two sweeps' tilings may meet the detector in different numbers of tiles
+        if (two) launch_fill_f64(partials, (long long)T * pl.per_step, 0.0, q);
+        int sw = 0, hc = 0, ec = 0;   // sweeps so far; PML copies holding the H-side and E-side auxiliaries
+        for (int n = 0; n < single; ++n, ++sw) {
+            const float* in = F[(start + sw) & 1];
+            float* out = F[(start + sw + 1) & 1];
+            launch_fwd_step(g, fwd, in, out, psi, hc, eps, wave[n], mwave(n), partials + (int64_t)n * pl.per_step, q);
+            hc ^= 1;
+            const int slice = slice_of(n);
+            if (slice >= 0) record(in, false, out, false, slice, q);
+        }
+        for (int n = single; n + 1 < T; n += 2, ++sw) {
+            const float* in = F[(start + sw) & 1];
+            float* out = F[(start + sw + 1) & 1];
+            const int s0 = slice_of(n), s1 = slice_of(n + 1);
+            const bool want_mid = (s0 >= 0 || s1 >= 0) && g.vps > 0;
+            launch_fwd2_step(g, fwd2, in, out, psi, hc, ec, eps, wave[n], wave[n + 1],
+                             partials + (int64_t)n * pl.per_step, partials + (int64_t)(n + 1) * pl.per_step,
+                             want_mid ? mid : nullptr, q);
+            hc ^= 1;
+            ec ^= 1;
+            if (s0 >= 0) record(in, false, mid, true, s0, q);    // E^n from the input, H^{n+1/2} intermediate
+            if (s1 >= 0) record(mid, true, out, false, s1, q);   // E^{n+1} intermediate, H^{n+3/2} from the output
         }
         launch_loss_final(partials, T, pl.per_step, loss, loss_series, q);
     };

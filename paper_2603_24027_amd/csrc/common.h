@@ -418,7 +418,7 @@ __device__ inline int slab_coord(int i, int n, int P) {   // -1 outside the slab
 // ----------------------------------------------------------------------------
 enum KernelKind {
     K_FILL = 0, K_FWD_STEP, K_REC_QUANT, K_LOSS_FINAL, K_INJECT, K_PRIM_REV, K_ADJ_STEP, K_SCALE_GRAD,
-    K_CODEC, K_PUT, K_RECORD, K_NUM_KINDS
+    K_CODEC, K_PUT, K_RECORD, K_FWD_STEP2, K_NUM_KINDS
 };
 
 // Defined in api.hip: hands out an event pair when timing is enabled.
@@ -441,9 +441,16 @@ void launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 struct Tiling;
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
                      const float* eps, float wave, float mwave, double* partials, hipStream_t s);
-// recorder of kept step `slice` of forward step n (F0: its input E^n, F1: its output H^{n+1/2})
-void launch_record(const Grid& g, const float* F0, const float* F1, void* store, float* staging, int slice,
-                   hipStream_t s);
+// two forward steps n, n+1 in one sweep (PML copies: H side hcopy, E side ecopy in;
+// the other copies out); p0, p1: the two steps' detector partials; mid: NULL or the
+// buffer that receives the intermediate step's recorder values
+void launch_fwd2_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy, int ecopy,
+                      const float* eps, float w0, float w1, double* p0, double* p1, float* mid, hipStream_t s);
+// recorder of kept step `slice` of forward step n: E^n on the high faces from E (a field
+// buffer, or when e_mid a buffer laid out as one kept step), H^{n+1/2} on the low faces
+// from H (likewise with h_mid)
+void launch_record(const Grid& g, const float* E, bool e_mid, const float* H, bool h_mid, void* store,
+                   float* staging, int slice, hipStream_t s);
 // scaled FP8 recorder: the staging values of one kept step, then the chunk maxima
 long long rec_quant_scratch_floats(const Grid& g);
 void launch_rec_quant(const Grid& g, const float* staging, void* store, int slice, hipStream_t s);

@@ -416,26 +416,38 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MS ? 4 
 }
 
 // Recorder of one kept step (Section 2: the interface slices are recorded during the
-// forward simulation): the tangential H^{n+1/2} of the three low faces (index P-1),
-// from the step's output buffer F1, and the tangential E^n of the three high faces
-// (index n-P), from its input buffer F0, each over the interior extent of its face, as
-// the 12 blocks of kept step `slice`: encoded to the storage type, or (scaled FP8) in
-// FP32 into the staging buffer that the two quantisation launches then encode.  One
-// thread per face cell and side, both tangential components.
+// forward simulation): the tangential H^{n+1/2} of the three low faces (index P-1) and
+// the tangential E^n of the three high faces (index n-P), each over the interior extent
+// of its face, as the 12 blocks of kept step `slice`: encoded to the storage type, or
+// (scaled FP8) in FP32 into the staging buffer that the two quantisation launches then
+// encode.  E^n comes from the step's input buffer, H^{n+1/2} from its output buffer,
+// or either from a buffer laid out as one kept step in FP32 (written by a two-step sweep,
+// whose intermediate fields never reach a field buffer).  One thread per face cell and
+// side, both tangential components.
 template <int DT>
-__global__ __launch_bounds__(256) void k_record(Grid g, const float* __restrict__ F0, const float* __restrict__ F1,
-                                                void* __restrict__ dst) {
+__global__ __launch_bounds__(256) void k_record(Grid g, const float* __restrict__ E, int e_mid,
+                                                const float* __restrict__ H, int h_mid, void* __restrict__ dst) {
     const int face = g.my * g.mz + g.mx * g.mz + g.mx * g.my;   // < 2^31: 24 N < 2^31
     int t = (int)blockIdx.x * 256 + (int)threadIdx.x;
     if (t >= 2 * face) return;
     const bool high = t >= face;
     if (high) t -= face;
     const FaceCell f = face_cell(g, t, high);
-    const long long N = g.N;
-    const float* A = high ? F0 : F1 + 3 * N;                   // E^n on the high faces, H^{n+1/2} on the low ones
-    const long long idx = f.x + (long long)g.nx * (f.y + (long long)g.ny * f.z);
-    store_code<DT>(dst, block_offset(g, f.blk) + f.u, A[f.c0 * N + idx]);
-    store_code<DT>(dst, block_offset(g, f.blk + 1) + f.u, A[f.c1 * N + idx]);
+    const long long o0 = block_offset(g, f.blk) + f.u, o1 = block_offset(g, f.blk + 1) + f.u;
+    float v0, v1;
+    if (high ? e_mid : h_mid) {
+        const float* A = high ? E : H;
+        v0 = A[o0];
+        v1 = A[o1];
+    } else {
+        const long long N = g.N;
+        const float* A = high ? E : H + 3 * N;                 // E^n on the high faces, H^{n+1/2} on the low ones
+        const long long idx = f.x + (long long)g.nx * (f.y + (long long)g.ny * f.z);
+        v0 = A[f.c0 * N + idx];
+        v1 = A[f.c1 * N + idx];
+    }
+    store_code<DT>(dst, o0, v0);
+    store_code<DT>(dst, o1, v1);
 }
 
 // FP8 recorder of one kept step, in two launches over (chunk, block) grids so that
@@ -523,13 +535,15 @@ void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1,
     else launch_fwd_step_t<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, s);
 }
 
-void launch_record(const Grid& g, const float* F0, const float* F1, void* store, float* staging, int slice,
-                   hipStream_t s) {
+void launch_record(const Grid& g, const float* E, bool e_mid, const float* H, bool h_mid, void* store,
+                   float* staging, int slice, hipStream_t s) {
     if (g.P == 0 || g.vps == 0) return;
     const long long n = g.vps / 2;                      // face cells on both sides
     const dim3 grid((unsigned)((n + 255) / 256)), block(256);
     void* dst = g.dtype == 3 ? (void*)staging : (void*)((char*)store + slice * g.slice_stride);
-    with_dtype(g.dtype, [&]<int DT>() { launch_kernel(K_RECORD, k_record<DT>, grid, block, s, g, F0, F1, dst); });
+    with_dtype(g.dtype, [&]<int DT>() {
+        launch_kernel(K_RECORD, k_record<DT>, grid, block, s, g, E, (int)e_mid, H, (int)h_mid, dst);
+    });
 }
 
 long long rec_quant_scratch_floats(const Grid& g) {

@@ -21,6 +21,7 @@ namespace fdtd {
 
 constexpr int TX = 64;        // cells per tile row (one wavefront)
 constexpr int EXT = TX + 2;   // LDS row length: tile plus a halo column on each side
+constexpr int W2 = TX - 4;    // owned columns of a two-step forward tile (two halo cells each side)
 
 struct Tiling {
     int ty;                   // rows per tile (threads in y)
