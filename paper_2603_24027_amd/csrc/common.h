@@ -16,9 +16,10 @@
 // Convolutional-PML auxiliaries live only in the slabs [0, P) and [n-P, n) of
 // their axis.  Slab of axis d, slab coordinate i' in [0, 2P):
 //   i' = i for i < P, i' = i - (n - 2P) for i >= n - P.
-// Within the PML buffer each axis owns four slab-sized arrays
-//   [H term a, H term b, E term a, E term b] with (a, b) = (3, 4) for x,
-//   (0, 5) for y and (1, 2) for z;  slab layouts (x fastest):
+// Within the PML buffer each axis owns two arrays of slab-sized cell pairs,
+//   [H (term a, term b) | E (term a, term b)] with (a, b) = (3, 4) for x,
+//   (0, 5) for y and (1, 2) for z, the two terms of a cell adjacent (one 64-bit
+//   access);  slab cell order (x fastest):
 //   x: i' + 2P (j + ny k),  y: i + nx (j' + 2P k),  z: i + nx (j + ny k').
 // The CPML coefficients depend on i' only (same thickness on every face),
 // so one table of 2P entries per node type serves all three axes:

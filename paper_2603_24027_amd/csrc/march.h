@@ -203,21 +203,22 @@ __device__ inline bool box_plane(const int lo[3], const int hi[3], int z, uint32
 }
 
 // Per-lane part of the byte offsets of a column's PML auxiliaries: x slab
-// sx + 2P y, y slab x + nx sy, z slab x + nx y (OOB outside the slab or when off).
+// sx + 2P y, y slab x + nx sy, z slab x + nx y, 8 bytes per cell (the pair of one axis
+// and side), OOB outside the slab or when off.
 struct PsiLane {
     uint32_t x, y, z;
 };
+__device__ inline uint32_t lane_off8(bool on, int idx) { return on ? (uint32_t)idx << 3 : OOB; }
 __device__ inline PsiLane psi_lane(const Grid& g, const Col& c, bool on) {
     PsiLane l;
-    l.x = lane_off(on && c.sx >= 0, c.sx + 2 * g.P * c.y);
-    l.y = lane_off(on && c.sy >= 0, c.x + g.nx * c.sy);
-    l.z = lane_off(on && c.xy >= 0 && g.P > 0, c.xy);
+    l.x = lane_off8(on && c.sx >= 0, c.sx + 2 * g.P * c.y);
+    l.y = lane_off8(on && c.sy >= 0, c.x + g.nx * c.sy);
+    l.z = lane_off8(on && c.xy >= 0 && g.P > 0, c.xy);
     return l;
 }
-// Plane-uniform part for one side (0 H, 1 E) on plane z of the copy at byte offset
-// `base`, and the distance to the second auxiliary of each slab.
+// Plane-uniform part for one side (0 H, 1 E) on plane z of the copy at byte offset `base`.
 struct PsiPlane {
-    uint32_t x, y, z, dx, dy, dz;
+    uint32_t x, y, z;
     bool zs;                  // plane z lies in a z slab
 };
 __device__ inline PsiPlane psi_plane(const Grid& g, int side, int z, uint32_t base) {
@@ -225,13 +226,27 @@ __device__ inline PsiPlane psi_plane(const Grid& g, int side, int z, uint32_t ba
     const int P = g.P;
     const int sz = P > 0 ? slab_coord(z, g.nz, P) : -1;
     p.zs = sz >= 0;
-    p.x = uni(base + ((uint32_t)(g.psi_off[0] + side * 2 * g.slab[0] + 2LL * P * g.ny * z) << 2));
-    p.y = uni(base + ((uint32_t)(g.psi_off[1] + side * 2 * g.slab[1] + 2LL * P * g.nx * z) << 2));
-    p.z = uni(base + ((uint32_t)(g.psi_off[2] + side * 2 * g.slab[2] + (long long)g.nx * g.ny * (p.zs ? sz : 0)) << 2));
-    p.dx = (uint32_t)g.slab[0] << 2;
-    p.dy = (uint32_t)g.slab[1] << 2;
-    p.dz = (uint32_t)g.slab[2] << 2;
+    p.x = uni(base + ((uint32_t)(g.psi_off[0] + side * 2 * g.slab[0]) << 2) + ((uint32_t)(2LL * P * g.ny * z) << 3));
+    p.y = uni(base + ((uint32_t)(g.psi_off[1] + side * 2 * g.slab[1]) << 2) + ((uint32_t)(2LL * P * g.nx * z) << 3));
+    p.z = uni(base + ((uint32_t)(g.psi_off[2] + side * 2 * g.slab[2]) << 2) +
+              ((uint32_t)((long long)g.nx * g.ny * (p.zs ? sz : 0)) << 3));
     return p;
+}
+// The two auxiliaries of one axis and side at one cell, in one 64-bit access.
+typedef uint32_t u32x2 __attribute__((vector_size(8)));   // the type the 64-bit buffer builtins take and return
+__device__ inline void bld2v(rsrc_t r, uint32_t v, uint32_t s, float& a, float& b) {
+    const u32x2 u = __builtin_amdgcn_raw_buffer_load_b64(r, v, s, FDTD_LD_AUX);
+    // each element through a scalar first: a bit cast of a vector element in place
+    // reads the vector's first element
+    const uint32_t lo = u[0], hi = u[1];
+    a = __builtin_bit_cast(float, lo);
+    b = __builtin_bit_cast(float, hi);
+}
+__device__ inline void bst2v(rsrc_t r, uint32_t v, uint32_t s, float a, float b) {
+    u32x2 u;
+    u[0] = __builtin_bit_cast(uint32_t, a);
+    u[1] = __builtin_bit_cast(uint32_t, b);
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, v, s, FDTD_ST_AUX);
 }
 // The six auxiliaries (x: 3, 4; y: 0, 5; z: 1, 2) of the axes whose slabs a tile of
 // class SL (bit 0: x, 1: y, 2: z) reaches; out-of-slab cells read 0 and their stores are
@@ -240,21 +255,15 @@ __device__ inline PsiPlane psi_plane(const Grid& g, int side, int z, uint32_t ba
 template <int SL>
 __device__ inline void bld_psi_s(rsrc_t r, const PsiLane& l, const PsiPlane& p, float v[6]) {
     v[0] = v[1] = v[2] = v[3] = v[4] = v[5] = 0.0f;
-    if constexpr ((SL & 1) != 0) { v[3] = bldv(r, l.x, p.x); v[4] = bldv(r, l.x, p.x + p.dx); }
-    if constexpr ((SL & 2) != 0) { v[0] = bldv(r, l.y, p.y); v[5] = bldv(r, l.y, p.y + p.dy); }
-    if constexpr ((SL & 4) != 0) {
-        const uint32_t vz = p.zs ? l.z : OOB;
-        v[1] = bldv(r, vz, p.z); v[2] = bldv(r, vz, p.z + p.dz);
-    }
+    if constexpr ((SL & 1) != 0) bld2v(r, l.x, p.x, v[3], v[4]);
+    if constexpr ((SL & 2) != 0) bld2v(r, l.y, p.y, v[0], v[5]);
+    if constexpr ((SL & 4) != 0) bld2v(r, p.zs ? l.z : OOB, p.z, v[1], v[2]);
 }
 template <int SL>
 __device__ inline void bst_psi_s(rsrc_t r, const PsiLane& l, const PsiPlane& p, const float v[6]) {
-    if constexpr ((SL & 1) != 0) { bstv(r, l.x, p.x, v[3]); bstv(r, l.x, p.x + p.dx, v[4]); }
-    if constexpr ((SL & 2) != 0) { bstv(r, l.y, p.y, v[0]); bstv(r, l.y, p.y + p.dy, v[5]); }
-    if constexpr ((SL & 4) != 0) {
-        const uint32_t vz = p.zs ? l.z : OOB;
-        bstv(r, vz, p.z, v[1]); bstv(r, vz, p.z + p.dz, v[2]);
-    }
+    if constexpr ((SL & 1) != 0) bst2v(r, l.x, p.x, v[3], v[4]);
+    if constexpr ((SL & 2) != 0) bst2v(r, l.y, p.y, v[0], v[5]);
+    if constexpr ((SL & 4) != 0) bst2v(r, p.zs ? l.z : OOB, p.z, v[1], v[2]);
 }
 
 // Class of a tile: which axes' PML slabs (bit 0: x, 1: y, 2: z) reach the cells
