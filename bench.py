@@ -63,8 +63,8 @@ COMPRESSED = {"c4": _FP8_BF16, "c4p": _FP8_BF16, "c5": _FP8_BF16}
 CACHE_RESIDENT = {"c2", "c3p", "c2pw", "c4crop", "c4pcrop", "c5crop"}
 DEFAULT_WORKLOAD = "c4"
 KERNEL_SOURCES = ["paper_2603_24027_amd/csrc/common.h", "paper_2603_24027_amd/csrc/march.h",
-                  "paper_2603_24027_amd/csrc/forward.hip", "paper_2603_24027_amd/csrc/reverse.hip",
-                  "paper_2603_24027_amd/csrc/api.hip"]
+                  "paper_2603_24027_amd/csrc/forward.hip", "paper_2603_24027_amd/csrc/forward2.hip",
+                  "paper_2603_24027_amd/csrc/reverse.hip", "paper_2603_24027_amd/csrc/api.hip"]
 
 
 def kernel_source_hash() -> str:

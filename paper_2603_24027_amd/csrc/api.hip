@@ -370,8 +370,14 @@ void tile_order(const Plan& pl, int which, std::vector<int32_t>& out) {
     for (int L = 0; L < t.count; ++L) by_class[cls[(size_t)L]].push_back(L);
     out.clear();
     out.reserve((size_t)t.count);
+    // single-step sweeps: the costliest classes first (class 7, all three slabs, down to
+    // class 0), so that the chunk's last blocks are cheap ones and its tail is short
+    // (256x256x128: forward 131.8 -> 126.2 us, adjoint 147.7 -> 142.2); the two-step
+    // sweep, whose launch is a few rounds of large blocks, measured 1 % slower that way
+    const bool costly_first = which != 2;
     for (int x = 0; x < 8; ++x)
-        for (int c = 0; c < 8; ++c) {
+        for (int i = 0; i < 8; ++i) {
+            const int c = costly_first ? 7 - i : i;
             const size_t n = by_class[c].size(), lo = n * x / 8, hi = n * (x + 1) / 8;
             out.insert(out.end(), by_class[c].begin() + (long)lo, by_class[c].begin() + (long)hi);
         }
