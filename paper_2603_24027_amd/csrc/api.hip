@@ -199,7 +199,13 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     g.dby0 = p->det_lo[1] / BY; g.dnby = (p->det_hi[1] - 1) / BY - g.dby0 + 1;
     g.dbz0 = p->det_lo[2];      g.dnbz = p->det_hi[2] - p->det_lo[2];
     Tiling& t = pl->fwd;
-    t.ty = env_int("FDTD_TILE_Y", 4) == 8 ? 8 : 4;
+    // 8-row tiles (fewer re-read ring rows per cell) unless the grid has fewer 8-row
+    // tiles than compute units; measured: 256x256x128 forward 126.4 -> 123.2 us, adjoint
+    // 142.4 -> 139.9, 512x512x256 adjoint 978 -> 962, 128^3 forward 28.2 -> 27.8, but
+    // 32^3 (16 tiles) forward 17.2 -> 19.9
+    const long long tiles8 = (long long)((p->nx + TX - 1) / TX) * ((p->ny + 7) / 8) * ((p->nz + 7) / 8);
+    const int ty_default = tiles8 >= 256 ? 8 : 4;
+    t.ty = env_int("FDTD_TILE_Y", ty_default) == 8 ? 8 : 4;
     t.cz = env_int("FDTD_TILE_Z", 8) == 4 ? 4 : 8;
     t.ntx = (p->nx + TX - 1) / TX;
     t.nty = (p->ny + t.ty - 1) / t.ty;
@@ -250,35 +256,35 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     }
     Tiling& a = pl->adj;
     a = t;
-    // 8-row tiles when the 4-row tiling fills the chip in one round (4 workgroups
-    // on each of 256 compute units): fewer halo rows at the same occupancy
-    const int adj_rounds4 = (t.ntx * ((p->ny + 3) / 4) * ((p->nz + 7) / 8) + 1023) / 1024;
-    a.ty = env_int("FDTD_ADJ_TILE_Y", adj_rounds4 <= 1 ? 8 : 4) == 8 ? 8 : 4;
+    a.ty = env_int("FDTD_ADJ_TILE_Y", ty_default) == 8 ? 8 : 4;
     a.cz = env_int("FDTD_ADJ_TILE_Z", 8) == 4 ? 4 : 8;
     a.nty = (p->ny + a.ty - 1) / a.ty;
     a.ntz = (p->nz + a.cz - 1) / a.cz;
     a.count = a.ntx * a.nty * a.ntz;
     Tiling& r = pl->rev;
     r = t;
-    r.ty = env_int("FDTD_REV_TILE_Y", 4) == 8 ? 8 : 4;
     pl->rev_x0 = pl->box_o[0] & ~31;
     r.ntx = (pl->box_o[0] + pl->box_n[0] - pl->rev_x0 + TX - 1) / TX;
-    r.nty = (pl->box_n[1] + r.ty - 1) / r.ty;
     {
-        // Depth of the reversal's tiles: among 4, 5 and 6 planes, the one whose tile count
-        // fills most of one round (five 4-wave workgroups on each of 256 compute units)
-        // when some depth fits in a round, else 6 (the least re-read z halo).  Measured at
-        // 128^3 (one round at depth 5: 22.0 -> 20.6 us) and 256x256x128 (depth 6).
-        const long long slots = 5 * 256, cols = (long long)r.ntx * r.nty;
+        // Shape of the reversal's tiles: 4 rows and, among 4, 5 and 6 planes, the depth whose
+        // tile count fills most of one round (five 4-wave workgroups on each of 256 compute
+        // units) when some depth fits in a round, else 6 (the least re-read z halo); 8 x 8
+        // where the 4 x 6 tiling takes more than eight rounds.  Measured at 128^3 (one round
+        // at depth 5: 22.0 -> 20.6 us), 256x256x128 (3.3 rounds: 4 x 6 88.2 us, 8 x 8 88.4)
+        // and 512x512x256 (29 rounds: 716 -> 696 us with 8 x 8).
+        const long long slots = 5 * 256, cols = (long long)r.ntx * ((pl->box_n[1] + 3) / 4);
         int pick = 6;
         long long best = 0;
         for (int cz = 4; cz <= 6; ++cz) {
             const long long n = cols * ((pl->box_n[2] + cz - 1) / cz);
             if (n <= slots && n > best) { best = n; pick = cz; }
         }
-        const int cz = env_int("FDTD_REV_TILE_Z", r.ty == 4 ? pick : 4);
+        const bool big = cols * ((pl->box_n[2] + 5) / 6) > 8 * slots;
+        r.ty = env_int("FDTD_REV_TILE_Y", big ? 8 : 4) == 8 ? 8 : 4;
+        const int cz = env_int("FDTD_REV_TILE_Z", r.ty == 4 ? pick : (big ? 8 : 4));
         r.cz = (cz == 8 || (r.ty == 4 && (cz == 5 || cz == 6))) ? cz : 4;
     }
+    r.nty = (pl->box_n[1] + r.ty - 1) / r.ty;
     r.ntz = (pl->box_n[2] + r.cz - 1) / r.cz;
     r.count = r.ntx * r.nty * r.ntz;
     pl->psi_floats = (uint64_t)g.psi_total;

@@ -113,27 +113,36 @@ __device__ __forceinline__ uint32_t src_plane(const Grid& g, int k, uint32_t lan
     return in ? lane_src : OOB;
 }
 
-// Straight-line loads of plane k's inputs (out-of-domain and out-of-slab values read as 0).
+// Loads of plane k's inputs (out-of-domain and out-of-slab values read as 0).
 template <int TY, int SL>
 __device__ __forceinline__ void load_plane_in(const Grid& g, const FwdBufs& b, const FwdLanes& L,
                                               const FwdCtx<TY>& c, int k, PlaneIn& d) {
     const uint32_t nb = (uint32_t)c.N << 2;
     const int z1 = bound(k + 1, g.nz, g.periodic);
     const uint32_t s1 = uni(z1 < 0 ? 0u : (uint32_t)(z1 * c.plane) << 2);
-    bld3v(b.F0, z1 < 0 ? OOB : L.eo, s1, nb, d.e1);
-    bld3v(b.F0, z1 < 0 ? OOB : L.er, s1, nb, d.er);
     const uint32_t sk = uni((uint32_t)(k * c.plane) << 2);
+    const PsiPlane pH = psi_plane(g, 0, k, b.hin), pE = psi_plane(g, 1, k, 0);
+    // loads that only some waves use (rows 0-3 hold the LDS ring, rows 0-1 the halo cells),
+    // issued first and only by those waves: the waits for the loads every wave issues
+    // below then cover them too, so the counts stay exact
+    #pragma unroll
+    for (int q = 0; q < 3; ++q) { d.er[q] = 0.0f; d.hh0[q] = 0.0f; }
+    #pragma unroll
+    for (int q = 0; q < 6; ++q) d.phh[q] = 0.0f;
+    if (c.row < 4) bld3v(b.F0, z1 < 0 ? OOB : L.er, s1, nb, d.er);
+    if (c.row < 2) {
+        bld3v(b.F0, L.hc, sk + 3 * nb, nb, d.hh0);
+        bld_psi_s<SL>(b.psi, L.ph, pH, d.phh);
+    }
+    bld3v(b.F0, z1 < 0 ? OOB : L.eo, s1, nb, d.e1);
     bld3v(b.F0, L.o, sk + 3 * nb, nb, d.h0);
-    bld3v(b.F0, L.hc, sk + 3 * nb, nb, d.hh0);
     const float ep = bldv(b.eps, L.o, sk);
     d.ep = c.live ? ep : 1.0f;
     uint32_t ss;
     const uint32_t vs = src_plane(g, k, L.src, ss);
     d.sp = bldv(b.src, vs, ss);
-    const PsiPlane pH = psi_plane(g, 0, k, b.hin), pE = psi_plane(g, 1, k, 0);
     bld_psi_s<SL>(b.psi, L.po, pH, d.ph);
     bld_psi_s<SL>(b.psi, L.po, pE, d.pe);
-    bld_psi_s<SL>(b.psi, L.ph, pH, d.phh);
 }
 
 // One plane k of the forward sweep: publish E^n(k+1) to LDS, H^{n+1/2}(k) on the own
