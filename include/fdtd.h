@@ -219,10 +219,12 @@ FDTD_API int store_config(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cf
  * arrays of the problem (source signal and profiles) are read before the call
  * returns: the few values they contribute travel as kernel arguments, so no
  * host memory is read by the device afterwards.
- * Tile shapes are chosen from the grid; the environment variables
- * FDTD_TILE_Y/Z (forward), FDTD_ADJ_TILE_Y/Z and FDTD_REV_TILE_Y/Z (the two
- * reverse sweeps) override them for tuning (Y: 4 or 8 rows; Z: planes per
- * tile, 4 or 8, and 5 or 6 for the reversal with 4 rows); results do not
+ * Tile shapes, and whether the forward advances one or two time steps per sweep,
+ * are chosen from the grid; the environment variables FDTD_TILE_Y/Z (forward),
+ * FDTD_ADJ_TILE_Y/Z and FDTD_REV_TILE_Y/Z (the two reverse sweeps) override the
+ * shapes for tuning (Y: 4 or 8 rows; Z: planes per tile, 4 or 8, and 5 or 6 for
+ * the reversal with 4 rows), FDTD_FWD_STEPS (1 or 2) the steps per forward sweep
+ * and FDTD_FWD2_TILE_Z (8 or 16) the depth of the two-step tiles; results do not
  * depend on them beyond FP32 rounding order.
  */
 FDTD_API int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg,

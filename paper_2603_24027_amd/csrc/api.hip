@@ -248,7 +248,8 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
         const int want = env_int("FDTD_FWD_STEPS", 0);
         const bool two = want == 2 || (want != 1 && 2LL * interior >= t2.count);
         pl->fwd_steps = (!has_m && two) ? 2 : 1;
-        if (pl->fwd_steps == 2) pl->per_step = std::max(pl->per_step, t2.dntx * t2.dnty * t2.dntz);
+        // room for either sweep's detector tiles (the unused entries are zeroed by the call)
+        pl->per_step = std::max(pl->per_step, t2.dntx * t2.dnty * t2.dntz);
     }
     for (int d = 0; d < 3; ++d) {
         pl->box_o[d] = P > 0 ? P - 1 : 0;
@@ -313,9 +314,11 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
         cfg->dtype == FDTD_STORE_FP8_E4M3_SCALED ? align_up((uint64_t)rec_quant_scratch_floats(g) * 4, 256) : 0;
     pl->ws_order_fwd = pl->ws_staging + staging;
     pl->ws_order_adj = pl->ws_order_fwd + align_up(4ull * pl->fwd.count, 256);
+    // the two-step sweep's order table and intermediate recorder values are reserved whether
+    // or not it is chosen, so that the size store_config reports does not depend on the choice
     pl->ws_order_fwd2 = pl->ws_order_adj + align_up(4ull * pl->adj.count, 256);
-    pl->ws_mid = pl->ws_order_fwd2 + (pl->fwd_steps == 2 ? align_up(4ull * pl->fwd2.count, 256) : 0);
-    pl->ws_fields = pl->ws_mid + (pl->fwd_steps == 2 ? align_up((uint64_t)g.vps * 4, 256) : 0);
+    pl->ws_mid = pl->ws_order_fwd2 + align_up(4ull * pl->fwd2.count, 256);
+    pl->ws_fields = pl->ws_mid + align_up((uint64_t)g.vps * 4, 256);
     // second primal and second adjoint field buffers (ping-pong)
     in.workspace_bytes = pl->ws_fields + 2 * in.fields_bytes;
     in.design_cells = (uint64_t)(p->des_hi[0] - p->des_lo[0]) * (p->des_hi[1] - p->des_lo[1]) *
@@ -637,7 +640,7 @@ int forward_with(const Plan& pl, const fdtd_problem_t* prob, const fdtd_store_cf
         launch_fill(F[start], 6 * N, 0.0f, q);
         launch_fill(psi, 2 * (long long)pl.psi_floats, 0.0f, q);
         // the two sweeps' tilings may meet the detector in different numbers of tiles
-        if (two) launch_fill_f64(partials, (long long)T * pl.per_step, 0.0, q);
+        launch_fill_f64(partials, (long long)T * pl.per_step, 0.0, q);
         int sw = 0, hc = 0, ec = 0;   // sweeps so far; PML copies holding the H-side and E-side auxiliaries
         for (int n = 0; n < single; ++n, ++sw) {
             const float* in = F[(start + sw) & 1];
