@@ -64,7 +64,8 @@ CACHE_RESIDENT = {"c2", "c3p", "c2pw", "c4crop", "c4pcrop", "c5crop"}
 DEFAULT_WORKLOAD = "c4"
 KERNEL_SOURCES = ["paper_2603_24027_amd/csrc/common.h", "paper_2603_24027_amd/csrc/march.h",
                   "paper_2603_24027_amd/csrc/forward.hip", "paper_2603_24027_amd/csrc/forward2.hip",
-                  "paper_2603_24027_amd/csrc/reverse.hip", "paper_2603_24027_amd/csrc/api.hip"]
+                  "paper_2603_24027_amd/csrc/reverse.hip", "paper_2603_24027_amd/csrc/reverse2.hip",
+                  "paper_2603_24027_amd/csrc/api.hip"]
 
 
 def kernel_source_hash() -> str:
@@ -400,15 +401,15 @@ def main():
     design_cells = int(np.prod(prob.design_shape))
     ab = algorithmic_bytes(prob, design_cells)
     kernels = {}
-    for name in ("fwd_step", "fwd2_step", "prim_rev", "adj_step"):
+    for name in ("fwd_step", "fwd2_step", "prim_rev", "prim_rev2", "adj_step"):
         if name not in ktimes or ktimes[name][0] == 0:
             continue
         launches, total_ms = ktimes[name]
         avg_s = total_ms / launches / 1e3
-        # the two-step forward sweep reads and writes every value once per launch (two steps)
-        a = ab["fwd_step"] if name == "fwd2_step" else ab[name]
+        # the two-step sweeps read and write every value once per launch (two steps)
+        a = {"fwd2_step": ab["fwd_step"], "prim_rev2": ab["prim_rev"]}.get(name, ab.get(name))
         kernels[name] = {"launches": launches, "avg_us": avg_s * 1e6, "alg_bytes": a, "GBps": a / avg_s / 1e9}
-        if name == "fwd2_step":
+        if name in ("fwd2_step", "prim_rev2"):
             kernels[name]["time_steps_per_launch"] = 2
     dominant = max(kernels, key=lambda n: kernels[n]["avg_us"] * kernels[n]["launches"])
     dk = kernels[dominant]
@@ -439,7 +440,8 @@ def main():
         "config": {"workload": prob.name, "grid": [prob.nx, prob.ny, prob.nz], "pml": prob.pml,
                    "time_steps": T, "store_dtype": dtype, "k": k, "design_cells": design_cells,
                    "wavelength_cells": prob.wavelength,
-                   "forward_steps_per_sweep": 2 if "fwd2_step" in kernels else 1},
+                   "forward_steps_per_sweep": 2 if "fwd2_step" in kernels else 1,
+                   "reverse_steps_per_primal_sweep": 2 if "prim_rev2" in kernels else 1},
         "boundary_store_GB": gobj.info.payload_bytes / 1e9,
         "roofline": roofline,
         "whole_step": {"alg_bytes_per_time_step": ab["step_min"], "GBps": round(step_gbs, 1),

@@ -268,6 +268,10 @@ FDTD_API int fdtd_forward_noalloc(const fdtd_problem_t* prob, const fdtd_store_c
  *               [z][y][x] order, accumulated over time in FP64
  *   rec         host, in/out: must come from the matching fdtd_forward; marked
  *               consumed (a second backward on it returns FDTD_ESTATE)
+ * Asynchronous like fdtd_forward.  Whether the reverse primal pass takes one or
+ * two time steps per sweep is chosen from the grid; FDTD_REV_STEPS (1 or 2)
+ * overrides it and FDTD_REV2_TILE_Z (8 or 16) sets the depth of the two-step
+ * tiles.  The two forms give the same gradient up to FP32 rounding order.
  */
 FDTD_API int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg,
                   const float* eps, float* fields, const void* store, void* workspace,

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB_NAME = "libfdtd_mi355x.so"
-SOURCES = ["api.hip", "forward.hip", "forward2.hip", "reverse.hip"]
+SOURCES = ["api.hip", "forward.hip", "forward2.hip", "reverse.hip", "reverse2.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -65,12 +65,15 @@ struct Plan {
     int fwd_steps = 1;     // forward steps per sweep (1, or 2 where the two-step sweep applies)
     Tiling adj;            // adjoint sweep: the whole grid
     Tiling rev;            // primal reversal: the interior plus its shell
+    Tiling rev2;           // two-step primal reversal: the interior
+    int rev_steps = 1;     // reverse primal steps per sweep (1, or 2 where the two-step sweep applies)
     int box_o[3], box_n[3];
     int rev_x0;                    // x origin of the primal-reversal tiles (128-byte aligned)
     fdtd_store_info_t info;
     uint64_t ws_coef = 0, ws_profile = 0, ws_partials = 0, ws_staging = 0, ws_fields = 0;
     uint64_t ws_order_fwd = 0, ws_order_adj = 0, ws_order_fwd2 = 0;   // tile-order tables
     uint64_t ws_mid = 0;           // intermediate recorder values of a two-step sweep (one kept step, FP32)
+    uint64_t ws_stash = 0;         // a two-step reversal's inputs of its second step's seed and gradient
     uint64_t psi_floats = 0;
     int per_step = 0;
     int64_t src_volume = 0;
@@ -286,6 +289,28 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
         r.cz = (cz == 8 || (r.ty == 4 && (cz == 5 || cz == 6))) ? cz : 4;
     }
     r.nty = (pl->box_n[1] + r.ty - 1) / r.ty;
+    {
+        // two reverse steps per sweep over the interior (60 x 12 columns, 16 planes); not with
+        // a magnetic-current sheet, and not on a periodic grid with PML
+        Tiling& r2 = pl->rev2;
+        r2 = t;
+        r2.ty = 12;
+        r2.cz = env_int("FDTD_REV2_TILE_Z", 16) == 8 ? 8 : 16;
+        const int mxi = n[0] - 2 * P, myi = n[1] - 2 * P, mzi = n[2] - 2 * P;
+        r2.ntx = (mxi + W2 - 1) / W2;
+        r2.nty = (myi + r2.ty - 1) / r2.ty;
+        r2.ntz = (mzi + r2.cz - 1) / r2.cz;
+        r2.count = r2.ntx * r2.nty * r2.ntz;
+        r2.order = nullptr;
+        // Chosen where its launch is at least eight rounds of one 16-wave block per compute
+        // unit: the reversal is bound by issue and latency more than by HBM, so the halved
+        // traffic pays for the recomputed halo only when the chip stays full.  Measured:
+        // 512x512x256 (4480 blocks) 694 -> 627 us per step; 256x256x128 (560) 78 -> 113;
+        // 128^3 (126) 19 -> 39.  FDTD_REV_STEPS=1 or 2 overrides the choice.
+        const bool able = !has_m && !(p->boundary && P > 0) && mxi > 0 && myi > 0 && mzi > 0;
+        const int want = env_int("FDTD_REV_STEPS", 0);
+        pl->rev_steps = (able && (want == 2 || (want != 1 && r2.count >= 8 * 256))) ? 2 : 1;
+    }
     r.ntz = (pl->box_n[2] + r.cz - 1) / r.cz;
     r.count = r.ntx * r.nty * r.ntz;
     pl->psi_floats = (uint64_t)g.psi_total;
@@ -318,7 +343,14 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     // or not it is chosen, so that the size store_config reports does not depend on the choice
     pl->ws_order_fwd2 = pl->ws_order_adj + align_up(4ull * pl->adj.count, 256);
     pl->ws_mid = pl->ws_order_fwd2 + align_up(4ull * pl->fwd2.count, 256);
-    pl->ws_fields = pl->ws_mid + align_up((uint64_t)g.vps * 4, 256);
+    pl->ws_stash = pl->ws_mid + align_up((uint64_t)g.vps * 4, 256);
+    {
+        const uint64_t ndet = (uint64_t)(p->det_hi[0] - p->det_lo[0]) * (p->det_hi[1] - p->det_lo[1]) *
+                              (p->det_hi[2] - p->det_lo[2]);
+        const uint64_t ndes = (uint64_t)(p->des_hi[0] - p->des_lo[0]) * (p->des_hi[1] - p->des_lo[1]) *
+                              (p->des_hi[2] - p->des_lo[2]);
+        pl->ws_fields = pl->ws_stash + align_up((6 * ndet + 4 * ndes) * 4, 256);
+    }
     // second primal and second adjoint field buffers (ping-pong)
     in.workspace_bytes = pl->ws_fields + 2 * in.fields_bytes;
     in.design_cells = (uint64_t)(p->des_hi[0] - p->des_lo[0]) * (p->des_hi[1] - p->des_lo[1]) *
@@ -448,7 +480,8 @@ int check_hip(const char* what) {
 
 // ---- per-kernel timing ------------------------------------------------------
 const char* kKindNames[K_NUM_KINDS] = {"fill", "fwd_step", "rec_quant", "loss_final", "inject_shell",
-                                       "prim_rev", "adj_step", "scale_grad", "codec", "put", "record", "fwd2_step"};
+                                       "prim_rev", "adj_step", "scale_grad", "codec", "put", "record", "fwd2_step",
+                                       "prim_rev2", "rev_pending"};
 constexpr size_t kMaxTimedLaunches = 1 << 16;
 
 struct Timing {
@@ -561,8 +594,8 @@ uint64_t call_key(const Plan& pl, int dir, const fdtd_store_cfg_t* cfg, std::ini
     uint64_t h = fnv1a(pl.hash, &dir, sizeof dir);
     h = fnv1a(h, cfg, sizeof *cfg);
     // the tile shapes (they can be changed between calls through the environment)
-    const int tiles[9] = {pl.fwd.ty, pl.fwd.cz, pl.adj.ty, pl.adj.cz, pl.rev.ty, pl.rev.cz,
-                          pl.fwd2.ty, pl.fwd2.cz, pl.fwd_steps};
+    const int tiles[11] = {pl.fwd.ty, pl.fwd.cz, pl.adj.ty, pl.adj.cz, pl.rev.ty, pl.rev.cz,
+                           pl.fwd2.ty, pl.fwd2.cz, pl.fwd_steps, pl.rev2.cz, pl.rev_steps};
     h = fnv1a(h, tiles, sizeof tiles);
     for (const void* p : ptrs) h = fnv1a(h, &p, sizeof p);
     return h;
@@ -749,6 +782,9 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
     const float* wave = prob->src_wave;
     auto mwave = [&](int n) { return pl.msrc_volume > 0 ? prob->msrc_wave[n] : 0.0f; };
     Tiling adj = pl.adj;
+    const bool two = pl.rev_steps == 2;
+    float* mid = (float*)(ws + pl.ws_mid);
+    float* stash = (float*)(ws + pl.ws_stash);
     std::vector<int32_t> order_adj;
     tile_order(pl, 1, order_adj);
     adj.order = (const int32_t*)(ws + pl.ws_order_adj);
@@ -769,20 +805,67 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
                             n >= 1 ? 1 : 0};
         };
         launch_inject_shell(g, ShellJob{Fp[0], Fp[0], store, none, interp_for(T - 1, T, k, ip), 0, 1}, q);   // H^{T-1/2}
-        launch_inject_shell(g, shell_for(T - 1, Fp[0], Fp[1]), q);
-        for (int n = T - 1; n >= 0; --n) {
-            const int st = T - 1 - n;
-            float* po = Fp[st & 1];
-            float* pn = Fp[(st + 1) & 1];
-            float* ao = Fa[st & 1];
-            float* an = Fa[(st + 1) & 1];
-            // the interior reversal reads the E part of the shell from po; the adjoint launch
-            // then writes the shell of step n-1: E into pn (which the reversal has just
-            // written: the input of step n-1), H into po (which it has finished reading)
-            launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], mwave(n), grad_eps, q);
-            ShellJob next{};
-            if (n >= 1) next = shell_for(n - 1, pn, po);
-            launch_adj_step(g, adj, ao, an, eps, adj_psi, st & 1, n >= 1 ? &next : nullptr, q);
+        if (!two) {
+            launch_inject_shell(g, shell_for(T - 1, Fp[0], Fp[1]), q);
+            for (int n = T - 1; n >= 0; --n) {
+                const int st = T - 1 - n;
+                float* po = Fp[st & 1];
+                float* pn = Fp[(st + 1) & 1];
+                float* ao = Fa[st & 1];
+                float* an = Fa[(st + 1) & 1];
+                // the interior reversal reads the E part of the shell from po; the adjoint launch
+                // then writes the shell of step n-1: E into pn (which the reversal has just
+                // written: the input of step n-1), H into po (which it has finished reading)
+                launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], mwave(n), grad_eps,
+                                q);
+                ShellJob next{};
+                if (n >= 1) next = shell_for(n - 1, pn, po);
+                launch_adj_step(g, adj, ao, an, eps, adj_psi, st & 1, n >= 1 ? &next : nullptr, q);
+            }
+        } else {
+            // Two reverse steps per primal sweep: a single step first when T is odd, then the
+            // pairs (m, m-1).  A pair needs step m's shell in mid (slice layout) and step m-1's
+            // shell in its buffers (E into its input, H into its output); the adjoint launch of
+            // the first step of the unit before writes the former, that of its second step the
+            // latter.  Primal buffers alternate per sweep, adjoint buffers per step.
+            auto mid_for = [&](int m) {
+                ShellJob j = shell_for(m, mid, mid);
+                j.slice = 1;
+                return j;
+            };
+            int u = 0;                    // primal sweeps so far
+            int n = T - 1;
+            if (T & 1) {
+                launch_inject_shell(g, shell_for(T - 1, Fp[0], Fp[1]), q);
+                float* ao = Fa[0];
+                float* an = Fa[1];
+                launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, Fp[0], Fp[1], eps, ao, wave[n], mwave(n),
+                                grad_eps, q);
+                ShellJob next{};
+                if (n >= 1) next = mid_for(n - 1);
+                launch_adj_step(g, adj, ao, an, eps, adj_psi, 0, n >= 1 ? &next : nullptr, q);
+                if (n >= 2) launch_inject_shell(g, shell_for(n - 2, Fp[1], Fp[0]), q);
+                u = 1;
+                n -= 1;
+            } else {
+                launch_inject_shell(g, mid_for(T - 1), q);
+                launch_inject_shell(g, shell_for(T - 2, Fp[0], Fp[1]), q);
+            }
+            for (; n >= 1; n -= 2, ++u) {
+                float* po = Fp[u & 1];
+                float* pn = Fp[(u + 1) & 1];
+                const int st = T - 1 - n;
+                float* a0 = Fa[st & 1];
+                float* a1 = Fa[(st + 1) & 1];
+                launch_rev2(g, pl.rev2, po, pn, eps, a0, wave[n], wave[n - 1], grad_eps, stash, mid, q);
+                // the next pair (n-2, n-3): step n-2's shell into mid, step n-3's into pn (its
+                // input: E) and po (its output: H)
+                ShellJob ja{}, jb{};
+                if (n >= 3) { ja = mid_for(n - 2); jb = shell_for(n - 3, pn, po); }
+                launch_adj_step(g, adj, a0, a1, eps, adj_psi, st & 1, n >= 3 ? &ja : nullptr, q);
+                launch_rev_pending(g, a1, grad_eps, stash, q);
+                launch_adj_step(g, adj, a1, a0, eps, adj_psi, (st + 1) & 1, n >= 3 ? &jb : nullptr, q);
+            }
         }
         if (grad_scale) launch_scale_grad(grad_eps, (long long)pl.info.design_cells, grad_scale, q);
     };

@@ -286,13 +286,15 @@ struct Interp {
 
 // The interface shell of one reverse step, written from the store into primal field
 // buffers: E at the high faces (interpolation qE) into FE when do_e, H at the low
-// faces (interpolation qH) into FH when do_h.
+// faces (interpolation qH) into FH when do_h; with slice set, both into FE laid out as
+// one kept step of the store (the intermediate step of a two-step reversal).
 struct ShellJob {
     float* FE;
     float* FH;
     const void* store;
     Interp qE, qH;
     int do_e, do_h;
+    int slice;
 };
 
 // Compile-time storage type versions (the sweeps are instantiated per type so
@@ -402,6 +404,43 @@ __device__ inline void loss_seeds(int loss, const float e[3], const float h[3], 
     }
 }
 
+// The owner of an interior cell on the design or detector box: this step's loss
+// derivatives (2 E^{n+1} for |E|^2; H- and E-terms for a flux) are added to Ebar and
+// Hbar in place (the adjoint sweep reads them seeded), and the gradient
+// epsbar -= (dt/eps^2) Ebar . (U - J) accumulates in FP64.  Eb0 is the adjoint field
+// buffer (Ebar, then Hbar at component stride g.N).
+__device__ inline void grad_and_seed(const Grid& g, float* __restrict__ Eb0, double* __restrict__ grad,
+                                              int x, int y, int z, int idx, const float e1[3], const float h[3],
+                                              float ep, const float u[3]) {
+    const bool det = in_box(x, y, z, g.det_lo, g.det_hi), des = in_box(x, y, z, g.des_lo, g.des_hi);
+    if (!det && !des) return;
+    const long long N = g.N;
+    float eb[3] = {Eb0[idx], Eb0[N + idx], Eb0[2 * N + idx]};
+    if (det) {
+        float gE[3], gH[3];
+        loss_seeds(g.loss, e1, h, gE, gH);
+        eb[0] += gE[0];
+        eb[1] += gE[1];
+        eb[2] += gE[2];
+        Eb0[idx] = eb[0];
+        Eb0[N + idx] = eb[1];
+        Eb0[2 * N + idx] = eb[2];
+        if (g.loss != 0) {
+            float* Hb0 = Eb0 + 3 * N;
+            Hb0[idx] += gH[0];
+            Hb0[N + idx] += gH[1];
+            Hb0[2 * N + idx] += gH[2];
+        }
+    }
+    if (des) {
+        const int dx = g.des_hi[0] - g.des_lo[0], dy = g.des_hi[1] - g.des_lo[1];
+        const int di = (x - g.des_lo[0]) + dx * ((y - g.des_lo[1]) + dy * (z - g.des_lo[2]));
+        const double ee = (double)ep;
+        const double s = (double)eb[0] * u[0] + (double)eb[1] * u[1] + (double)eb[2] * u[2];
+        grad[di] -= (double)g.dt / (ee * ee) * s;
+    }
+}
+
 // dt / eps of the E update; the forward step, its reversal and its adjoint all use
 // this one expression, so that they agree bit for bit.
 __device__ inline float dt_over_eps(float dt, float ep) { return __fdividef(dt, ep); }
@@ -419,7 +458,7 @@ __device__ inline int slab_coord(int i, int n, int P) {   // -1 outside the slab
 // ----------------------------------------------------------------------------
 enum KernelKind {
     K_FILL = 0, K_FWD_STEP, K_REC_QUANT, K_LOSS_FINAL, K_INJECT, K_PRIM_REV, K_ADJ_STEP, K_SCALE_GRAD,
-    K_CODEC, K_PUT, K_RECORD, K_FWD_STEP2, K_NUM_KINDS
+    K_CODEC, K_PUT, K_RECORD, K_FWD_STEP2, K_PRIM_REV2, K_REV_PENDING, K_NUM_KINDS
 };
 
 // Defined in api.hip: hands out an event pair when timing is enabled.
@@ -458,6 +497,13 @@ void launch_rec_quant(const Grid& g, const float* staging, void* store, int slic
 void launch_loss_final(const double* partials, int steps, int per_step, double* loss, double* series,
                        hipStream_t s);
 void launch_inject_shell(const Grid& g, const ShellJob& job, hipStream_t s);
+// two reverse steps n, n-1 of the primal interior in one sweep (F0 -> F1), with step n's
+// gradient and loss seed (adjoint E of step n in Eb0) and, for step n-1, the values its
+// seed and gradient need kept in stash; mid: step n's interface shell (one kept step)
+void launch_rev2(const Grid& g, const Tiling& t, const float* F0, float* F1, const float* eps, float* Eb0,
+                 float wave_n, float wave_n1, double* grad, float* stash, const float* mid, hipStream_t s);
+// step n-1's loss seed into the adjoint fields A (E then H) and its gradient term, from stash
+void launch_rev_pending(const Grid& g, float* A, double* grad, const float* stash, hipStream_t s);
 void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
                      const float* F0, float* F1, const float* eps, float* Eb0, float wave, float mwave,
                      double* grad, hipStream_t s);

@@ -268,12 +268,18 @@ __device__ inline void shell_cell(const Grid& g, const ShellJob& j, int t) {
     if (high) t -= face;
     if (t >= face || (high ? !j.do_e : !j.do_h)) return;
     const FaceCell f = face_cell(g, t, high);
+    const Interp& q = high ? j.qE : j.qH;
+    const float v0 = shell_value_t<DT>(g, j.store, q, f.blk, f.u), v1 = shell_value_t<DT>(g, j.store, q, f.blk + 1, f.u);
+    if (j.slice) {                                            // one kept step's layout, both sides in FE
+        j.FE[block_offset(g, f.blk) + f.u] = v0;
+        j.FE[block_offset(g, f.blk + 1) + f.u] = v1;
+        return;
+    }
     const long long N = g.N;
     float* A = high ? j.FE : j.FH + 3 * N;                    // E for the high faces, H for the low ones
-    const Interp& q = high ? j.qE : j.qH;
     const long long idx = f.x + (long long)g.nx * (f.y + (long long)g.ny * f.z);
-    A[f.c0 * N + idx] = shell_value_t<DT>(g, j.store, q, f.blk, f.u);
-    A[f.c1 * N + idx] = shell_value_t<DT>(g, j.store, q, f.blk + 1, f.u);
+    A[f.c0 * N + idx] = v0;
+    A[f.c1 * N + idx] = v1;
 }
 
 // the storage type is uniform over the launch: one branch per wave
@@ -558,43 +564,6 @@ __device__ __forceinline__ void e_rev(const Grid& g, const float (*hc)[TY + 2][E
     e[0] = interior ? e1[0] - cc * u[0] : e1[0];
     e[1] = interior ? e1[1] - cc * u[1] : e1[1];
     e[2] = interior ? e1[2] - cc * u[2] : e1[2];
-}
-
-// The owner of an interior cell on the design or detector box: this step's loss
-// derivatives (2 E^{n+1} for |E|^2; H- and E-terms for a flux) are added to Ebar and
-// Hbar in place (the adjoint sweep reads them seeded), and the gradient
-// epsbar -= (dt/eps^2) Ebar . (U - J) accumulates in FP64.  Eb0 is the adjoint field
-// buffer (Ebar, then Hbar at component stride g.N).
-__device__ __forceinline__ void grad_and_seed(const Grid& g, float* __restrict__ Eb0, double* __restrict__ grad,
-                                              int x, int y, int z, int idx, const float e1[3], const float h[3],
-                                              float ep, const float u[3]) {
-    const bool det = in_box(x, y, z, g.det_lo, g.det_hi), des = in_box(x, y, z, g.des_lo, g.des_hi);
-    if (!det && !des) return;
-    const long long N = g.N;
-    float eb[3] = {Eb0[idx], Eb0[N + idx], Eb0[2 * N + idx]};
-    if (det) {
-        float gE[3], gH[3];
-        loss_seeds(g.loss, e1, h, gE, gH);
-        eb[0] += gE[0];
-        eb[1] += gE[1];
-        eb[2] += gE[2];
-        Eb0[idx] = eb[0];
-        Eb0[N + idx] = eb[1];
-        Eb0[2 * N + idx] = eb[2];
-        if (g.loss != 0) {
-            float* Hb0 = Eb0 + 3 * N;
-            Hb0[idx] += gH[0];
-            Hb0[N + idx] += gH[1];
-            Hb0[2 * N + idx] += gH[2];
-        }
-    }
-    if (des) {
-        const int dx = g.des_hi[0] - g.des_lo[0], dy = g.des_hi[1] - g.des_lo[1];
-        const int di = (x - g.des_lo[0]) + dx * ((y - g.des_lo[1]) + dy * (z - g.des_lo[2]));
-        const double ee = (double)ep;
-        const double s = (double)eb[0] * u[0] + (double)eb[1] * u[1] + (double)eb[2] * u[2];
-        grad[di] -= (double)g.dt / (ee * ee) * s;
-    }
 }
 
 // E^n of plane z on the own cell (written by its owner, with gradient and seed) and the

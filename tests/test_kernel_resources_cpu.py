@@ -35,8 +35,8 @@ def usage():
         pytest.skip("hipcc not available")
     import sys
     sys.path.insert(0, ROOT)
-    with ThreadPoolExecutor(2) as ex:
-        texts = list(ex.map(_remarks, ["forward.hip", "reverse.hip", "forward2.hip"]))
+    with ThreadPoolExecutor(4) as ex:
+        texts = list(ex.map(_remarks, ["forward.hip", "reverse.hip", "forward2.hip", "reverse2.hip"]))
     out = {}
     for text in texts:
         for block in re.split(r"remark: Function Name: ", text)[1:]:
@@ -62,3 +62,11 @@ def test_two_step_sweep_keeps_four_waves(usage):
     for name, u in found.items():
         assert u["occupancy"] >= 4, (name, u)
         assert u["scratch"] <= 128, (name, u)
+
+
+def test_two_step_reversal_keeps_four_waves_and_no_scratch(usage):
+    found = {n: u for n, u in usage.items() if "k_rev2" in n}
+    assert found, "no k_rev2 instantiation in the remarks"
+    for name, u in found.items():
+        assert u["occupancy"] >= 4, (name, u)
+        assert u["scratch"] == 0, (name, u)
