@@ -387,6 +387,16 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
 // all land on the first and last XCD), and within a chunk the tiles come class by class,
 // each class in x-y-z order (neighbouring tiles share halo lines in that XCD's L2, and
 // the blocks running side by side mostly share one class's code).
+// A forward launch (one or two steps per sweep) of more than two rounds of the chip
+// (a compute unit holds two 8-wave, four 4-wave or one 16-wave workgroup), and an
+// adjoint launch of at least eight, is ordered by octants instead: the tile grid halved
+// along each axis, octant after octant (an XCD's chunk is then one octant when the
+// halves are equal), costliest class first within an octant.  Every octant holds one
+// PML side of each axis, so the chunks carry equal work on a symmetric grid.  Measured:
+// 512x512x256 adjoint 952 -> 915 us (32 rounds), two-step forward 1622 -> 1606 us;
+// 256x256x128 (4 rounds) forward 124.2 -> 121.4 but adjoint 140.5 -> 141.7; launches
+// of one round (128^3) ran 15-20 % slower that way.
+// FDTD_TILE_ORDER=1 (classes dealt out) or 2 (octants) overrides the choice.
 // which: 0 forward, 1 adjoint, 2 two-step forward.
 void tile_order(const Plan& pl, int which, std::vector<int32_t>& out) {
     const Tiling& t = which == 0 ? pl.fwd : (which == 1 ? pl.adj : pl.fwd2);
@@ -406,11 +416,36 @@ void tile_order(const Plan& pl, int which, std::vector<int32_t>& out) {
         cls[(size_t)L] = c;
         ++counts[c];
     }
+    out.clear();
+    out.reserve((size_t)t.count);
+    // twice the rounds of the chip the launch takes, rounded down
+    const long long rounds_x2 = which == 2 ? 2LL * t.count / 256 : 2LL * t.count * t.ty / (16 * 256);
+    const int want = env_int("FDTD_TILE_ORDER", 0);
+    const bool by_rounds = which == 1 ? rounds_x2 >= 16 : rounds_x2 > 4;
+    if (want == 2 || (want != 1 && by_rounds)) {
+        const int n[3] = {t.ntx, t.nty, t.ntz};
+        const int h[3] = {(t.ntx + 1) / 2, (t.nty + 1) / 2, (t.ntz + 1) / 2};
+        std::vector<int32_t> part;
+        for (int o = 0; o < 8; ++o) {
+            int lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                const bool up = ((o >> d) & 1) != 0;
+                lo[d] = up ? h[d] : 0;
+                hi[d] = up ? n[d] : h[d];
+            }
+            part.clear();
+            for (int z = lo[2]; z < hi[2]; ++z)
+                for (int y = lo[1]; y < hi[1]; ++y)
+                    for (int x = lo[0]; x < hi[0]; ++x) part.push_back(x + t.ntx * (y + t.nty * z));
+            std::stable_sort(part.begin(), part.end(),
+                             [&](int32_t a, int32_t b) { return cls[(size_t)a] > cls[(size_t)b]; });
+            out.insert(out.end(), part.begin(), part.end());
+        }
+        return;
+    }
     std::vector<int32_t> by_class[8];
     for (int c = 0; c < 8; ++c) by_class[c].reserve((size_t)counts[c]);
     for (int L = 0; L < t.count; ++L) by_class[cls[(size_t)L]].push_back(L);
-    out.clear();
-    out.reserve((size_t)t.count);
     // single-step sweeps: the costliest classes first (class 7, all three slabs, down to
     // class 0), so that the chunk's last blocks are cheap ones and its tail is short
     // (256x256x128: forward 131.8 -> 126.2 us, adjoint 147.7 -> 142.2); the two-step
@@ -569,19 +604,19 @@ int run_sequence(uint64_t key, hipStream_t s, Enqueue&& enqueue, const char* wha
     const hipError_t ce = hipStreamEndCapture(cap, &graph);
     if (ce != hipSuccess || !graph) return fail(FDTD_EHIP, "%s: stream capture failed: %s", what, hipGetErrorString(ce));
     const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return fail(FDTD_EHIP, "%s: graph instantiation failed: %s", what, hipGetErrorString(ie));
     hipEvent_t done = nullptr;
     if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
-        hipGraphExecDestroy(exec);
+        (void)hipGraphExecDestroy(exec);
         return fail(FDTD_EHIP, "%s: event creation failed", what);
     }
     if (g_graphs.entries.size() >= kMaxGraphs) {
         // the oldest graph may still run on some stream: wait for its last launch
         GraphEntry& old = g_graphs.entries.front();
-        hipEventSynchronize(old.done);
-        hipGraphExecDestroy(old.exec);
-        hipEventDestroy(old.done);
+        (void)hipEventSynchronize(old.done);
+        (void)hipGraphExecDestroy(old.exec);
+        (void)hipEventDestroy(old.done);
         g_graphs.entries.erase(g_graphs.entries.begin());
     }
     g_graphs.entries.push_back(GraphEntry{key, exec, done});
@@ -593,9 +628,11 @@ int run_sequence(uint64_t key, hipStream_t s, Enqueue&& enqueue, const char* wha
 uint64_t call_key(const Plan& pl, int dir, const fdtd_store_cfg_t* cfg, std::initializer_list<const void*> ptrs) {
     uint64_t h = fnv1a(pl.hash, &dir, sizeof dir);
     h = fnv1a(h, cfg, sizeof *cfg);
-    // the tile shapes (they can be changed between calls through the environment)
-    const int tiles[11] = {pl.fwd.ty, pl.fwd.cz, pl.adj.ty, pl.adj.cz, pl.rev.ty, pl.rev.cz,
-                           pl.fwd2.ty, pl.fwd2.cz, pl.fwd_steps, pl.rev2.cz, pl.rev_steps};
+    // the tile shapes and the launch-order choice (they can be changed between calls
+    // through the environment)
+    const int tiles[12] = {pl.fwd.ty, pl.fwd.cz, pl.adj.ty, pl.adj.cz, pl.rev.ty, pl.rev.cz,
+                           pl.fwd2.ty, pl.fwd2.cz, pl.fwd_steps, pl.rev2.cz, pl.rev_steps,
+                           env_int("FDTD_TILE_ORDER", 0)};
     h = fnv1a(h, tiles, sizeof tiles);
     for (const void* p : ptrs) h = fnv1a(h, &p, sizeof p);
     return h;

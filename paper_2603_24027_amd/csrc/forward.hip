@@ -278,7 +278,7 @@ __device__ __forceinline__ double fwd_tile(const Grid& g, const FwdBufs& b, cons
         bld_psi_s<SL>(b.psi, lm, pm, p);
         float mpm = 0.0f;
         if constexpr (MS) {
-            uint32_t msm;
+            uint32_t msm = 0;
             const bool mzm = zm >= 0 && box_plane(g.msrc_lo, g.msrc_hi, zm, msm);
             mpm = bldv(b.msrc, mzm ? Ln.m : OOB, msm);
         }

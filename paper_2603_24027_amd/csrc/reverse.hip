@@ -527,7 +527,7 @@ __device__ __forceinline__ void load_rev_in(const Grid& g, const RevBufs& b, con
     const float ep = bldv(b.eps, zi ? L.e : OOB, s1), xep = bldv(b.eps, zi ? L.xe : OOB, s1);
     d.ep = ep == 0.0f ? 1.0f : ep;      // positions that are not interior read 0
     d.xep = xep == 0.0f ? 1.0f : xep;
-    uint32_t ss;
+    uint32_t ss = 0;
     const bool sz = z1 >= 0 && src_z(g, z1, ss);
     d.sp = bldv(b.src, sz ? L.src : OOB, ss);
     d.xsp = bldv(b.src, sz ? L.xsrc : OOB, ss);

@@ -413,6 +413,28 @@ def test_every_tile_shape_against_oracle(tiles, case, monkeypatch):
     assert cos >= 0.9999 and r <= 1e-2
 
 
+@pytest.mark.parametrize("case,steps", [("ragged", 1), ("kappa", 1), ("c1", 1), ("periodic", 1), ("ragged", 2),
+                                        ("kappa", 2)])
+def test_launch_orders_give_the_same_bits(case, steps, monkeypatch):
+    # the order table only decides where each tile's workgroup runs (loss partials are
+    # indexed by tile), so the class-dealt and the octant orders agree bit for bit, with
+    # one or two forward steps per sweep; the octant order is checked against the oracle
+    require_gpu()
+    prob = CASES[case]()
+    monkeypatch.setenv("FDTD_FWD_STEPS", str(steps))
+    say("launch orders", case, "forward steps per sweep", steps)
+    outs = []
+    for order in ("1", "2"):
+        monkeypatch.setenv("FDTD_TILE_ORDER", order)
+        outs.append(gpu_run(prob, keep_fields=False))
+    assert outs[0]["loss"] == outs[1]["loss"]
+    assert np.array_equal(outs[0]["grad"], outs[1]["grad"])
+    L, g = adjoint.grad_time_reversal(prob, "fp64", 1, match_fp32=True)
+    r = rel(outs[1]["grad"], g)
+    say("  octant order vs oracle: rel-L2 %.3e" % r)
+    assert abs(outs[1]["loss"] - L) <= 1e-5 * abs(L) and r <= 1e-4
+
+
 def test_graph_cache_eviction_with_calls_in_flight():
     """More distinct calls than the graph cache keeps, enqueued without synchronising:
     evicting a graph waits for its last launch, and every result equals the eager one."""
