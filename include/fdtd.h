@@ -225,9 +225,9 @@ FDTD_API int store_config(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cf
  * shapes for tuning (Y: 4 or 8 rows; Z: planes per tile, 4 or 8, and 5 or 6 for
  * the reversal with 4 rows), FDTD_FWD_STEPS (1 or 2) the steps per forward sweep
  * and FDTD_FWD2_TILE_Z (8 or 16) the depth of the two-step tiles, FDTD_TILE_ORDER
- * (1: tile classes dealt out over the XCDs, 2: octants) the launch order of the
- * forward (one or two steps per sweep) and adjoint sweeps; results do not depend on
- * them beyond FP32 rounding order (on the launch order not at all).
+ * (1: the default order of small grids, 2: octants) the launch order of every
+ * sweep; results do not depend on them beyond FP32 rounding order (on the launch
+ * order not at all).
  */
 FDTD_API int fdtd_forward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg,
                  const float* eps, float* fields, float* psi, void* store, void* workspace,

@@ -72,6 +72,7 @@ struct Plan {
     fdtd_store_info_t info;
     uint64_t ws_coef = 0, ws_profile = 0, ws_partials = 0, ws_staging = 0, ws_fields = 0;
     uint64_t ws_order_fwd = 0, ws_order_adj = 0, ws_order_fwd2 = 0;   // tile-order tables
+    uint64_t ws_order_rev = 0, ws_order_rev2 = 0;
     uint64_t ws_mid = 0;           // intermediate recorder values of a two-step sweep (one kept step, FP32)
     uint64_t ws_stash = 0;         // a two-step reversal's inputs of its second step's seed and gradient
     uint64_t psi_floats = 0;
@@ -342,7 +343,9 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
     // the two-step sweep's order table and intermediate recorder values are reserved whether
     // or not it is chosen, so that the size store_config reports does not depend on the choice
     pl->ws_order_fwd2 = pl->ws_order_adj + align_up(4ull * pl->adj.count, 256);
-    pl->ws_mid = pl->ws_order_fwd2 + align_up(4ull * pl->fwd2.count, 256);
+    pl->ws_order_rev = pl->ws_order_fwd2 + align_up(4ull * pl->fwd2.count, 256);
+    pl->ws_order_rev2 = pl->ws_order_rev + align_up(4ull * pl->rev.count, 256);
+    pl->ws_mid = pl->ws_order_rev2 + align_up(4ull * pl->rev2.count, 256);
     pl->ws_stash = pl->ws_mid + align_up((uint64_t)g.vps * 4, 256);
     {
         const uint64_t ndet = (uint64_t)(p->det_hi[0] - p->det_lo[0]) * (p->det_hi[1] - p->det_lo[1]) *
@@ -396,17 +399,30 @@ int make_plan(const fdtd_problem_t* p, const fdtd_store_cfg_t* cfg, Plan* pl) {
 // 512x512x256 adjoint 952 -> 915 us (32 rounds), two-step forward 1622 -> 1606 us;
 // 256x256x128 (4 rounds) forward 124.2 -> 121.4 but adjoint 140.5 -> 141.7; launches
 // of one round (128^3) ran 15-20 % slower that way.
-// FDTD_TILE_ORDER=1 (classes dealt out) or 2 (octants) overrides the choice.
-// which: 0 forward, 1 adjoint, 2 two-step forward.
+// The primal reversal's tiles (one or two steps per sweep) all run one code path; by
+// default they go in x-y-z order dealt out in chunks (no table).  The one-step reversal
+// goes by octants where its launch takes more than two rounds: 256x256x128 reversal
+// 87.4 -> 84.2 us (the adjoint after it 140.4 -> 141.7), while 128^3 (one round) went
+// 19.0 -> 21.6.  The two-step reversal keeps its natural order (512x512x256 by
+// octants: 1246 -> 1379 us).
+// FDTD_TILE_ORDER=1 (classes dealt out, or no table) or 2 (octants) overrides the choice.
+// which: 0 forward, 1 adjoint, 2 two-step forward, 3 reversal, 4 two-step reversal; an
+// empty table means the reversal keeps its natural order.
 void tile_order(const Plan& pl, int which, std::vector<int32_t>& out) {
-    const Tiling& t = which == 0 ? pl.fwd : (which == 1 ? pl.adj : pl.fwd2);
+    const Tiling& t = which == 0 ? pl.fwd
+                      : which == 1 ? pl.adj
+                      : which == 2 ? pl.fwd2
+                      : which == 3 ? pl.rev
+                                   : pl.rev2;
     std::vector<int32_t> cls((size_t)t.count);
     int counts[8] = {0};
     for (int L = 0; L < t.count; ++L) {
         const int tix = L % t.ntx, tiy = (L / t.ntx) % t.nty, tiz = L / (t.ntx * t.nty);
         const int j0 = tiy * t.ty, k0 = tiz * t.cz;
-        int c;
-        if (which == 2) {
+        int c = 0;
+        if (which >= 3) {
+            // one code path for every tile
+        } else if (which == 2) {
             const int a = tix * W2;   // the two-step tile reads two cells around its own
             c = slab_class(pl.g, a - 2, a + TX - 3, j0 - 2, j0 + t.ty + 1, k0 - 2, k0 + t.cz);
         } else {
@@ -418,10 +434,10 @@ void tile_order(const Plan& pl, int which, std::vector<int32_t>& out) {
     }
     out.clear();
     out.reserve((size_t)t.count);
-    // twice the rounds of the chip the launch takes, rounded down
-    const long long rounds_x2 = which == 2 ? 2LL * t.count / 256 : 2LL * t.count * t.ty / (16 * 256);
+    // twice the rounds of the chip the launch takes, rounded down (16 waves per compute unit)
+    const long long rounds_x2 = (which == 2 || which == 4) ? 2LL * t.count / 256 : 2LL * t.count * t.ty / (16 * 256);
     const int want = env_int("FDTD_TILE_ORDER", 0);
-    const bool by_rounds = which == 1 ? rounds_x2 >= 16 : rounds_x2 > 4;
+    const bool by_rounds = which == 4 ? false : (which == 1 ? rounds_x2 >= 16 : rounds_x2 > 4);
     if (want == 2 || (want != 1 && by_rounds)) {
         const int n[3] = {t.ntx, t.nty, t.ntz};
         const int h[3] = {(t.ntx + 1) / 2, (t.nty + 1) / 2, (t.ntz + 1) / 2};
@@ -443,6 +459,7 @@ void tile_order(const Plan& pl, int which, std::vector<int32_t>& out) {
         }
         return;
     }
+    if (which >= 3) return;   // natural order
     std::vector<int32_t> by_class[8];
     for (int c = 0; c < 8; ++c) by_class[c].reserve((size_t)counts[c]);
     for (int L = 0; L < t.count; ++L) by_class[cls[(size_t)L]].push_back(L);
@@ -822,12 +839,21 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
     const bool two = pl.rev_steps == 2;
     float* mid = (float*)(ws + pl.ws_mid);
     float* stash = (float*)(ws + pl.ws_stash);
-    std::vector<int32_t> order_adj;
+    std::vector<int32_t> order_adj, order_rev, order_rev2;
     tile_order(pl, 1, order_adj);
     adj.order = (const int32_t*)(ws + pl.ws_order_adj);
+    Tiling rev = pl.rev, rev2 = pl.rev2;
+    tile_order(pl, 3, order_rev);
+    if (!order_rev.empty()) rev.order = (const int32_t*)(ws + pl.ws_order_rev);
+    if (two) {
+        tile_order(pl, 4, order_rev2);
+        if (!order_rev2.empty()) rev2.order = (const int32_t*)(ws + pl.ws_order_rev2);
+    }
     auto enqueue = [&](hipStream_t q) {
         put_tables(pl, prob, ws, q);
         launch_put(ws + pl.ws_order_adj, order_adj.data(), (long long)order_adj.size(), q);
+        if (rev.order) launch_put(ws + pl.ws_order_rev, order_rev.data(), (long long)order_rev.size(), q);
+        if (rev2.order) launch_put(ws + pl.ws_order_rev2, order_rev2.data(), (long long)order_rev2.size(), q);
         launch_fill(Fa[0], 6 * N, 0.0f, q);
         launch_fill(adj_psi, 2 * (long long)pl.psi_floats, 0.0f, q);
         launch_fill_f64(grad_eps, (long long)pl.info.design_cells, 0.0, q);
@@ -853,7 +879,7 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
                 // the interior reversal reads the E part of the shell from po; the adjoint launch
                 // then writes the shell of step n-1: E into pn (which the reversal has just
                 // written: the input of step n-1), H into po (which it has finished reading)
-                launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], mwave(n), grad_eps,
+                launch_prim_rev(g, rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], mwave(n), grad_eps,
                                 q);
                 ShellJob next{};
                 if (n >= 1) next = shell_for(n - 1, pn, po);
@@ -876,7 +902,7 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
                 launch_inject_shell(g, shell_for(T - 1, Fp[0], Fp[1]), q);
                 float* ao = Fa[0];
                 float* an = Fa[1];
-                launch_prim_rev(g, pl.rev, pl.box_o, pl.box_n, pl.rev_x0, Fp[0], Fp[1], eps, ao, wave[n], mwave(n),
+                launch_prim_rev(g, rev, pl.box_o, pl.box_n, pl.rev_x0, Fp[0], Fp[1], eps, ao, wave[n], mwave(n),
                                 grad_eps, q);
                 ShellJob next{};
                 if (n >= 1) next = mid_for(n - 1);
@@ -894,7 +920,7 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
                 const int st = T - 1 - n;
                 float* a0 = Fa[st & 1];
                 float* a1 = Fa[(st + 1) & 1];
-                launch_rev2(g, pl.rev2, po, pn, eps, a0, wave[n], wave[n - 1], grad_eps, stash, mid, q);
+                launch_rev2(g, rev2, po, pn, eps, a0, wave[n], wave[n - 1], grad_eps, stash, mid, q);
                 // the next pair (n-2, n-3): step n-2's shell into mid, step n-3's into pn (its
                 // input: E) and po (its output: H)
                 ShellJob ja{}, jb{};

@@ -417,12 +417,14 @@ def test_every_tile_shape_against_oracle(tiles, case, monkeypatch):
                                         ("kappa", 2)])
 def test_launch_orders_give_the_same_bits(case, steps, monkeypatch):
     # the order table only decides where each tile's workgroup runs (loss partials are
-    # indexed by tile), so the class-dealt and the octant orders agree bit for bit, with
-    # one or two forward steps per sweep; the octant order is checked against the oracle
+    # indexed by tile), so the default and the octant orders agree bit for bit, with one
+    # or two steps per forward and per reverse primal sweep; the octant order is checked
+    # against the oracle
     require_gpu()
     prob = CASES[case]()
     monkeypatch.setenv("FDTD_FWD_STEPS", str(steps))
-    say("launch orders", case, "forward steps per sweep", steps)
+    monkeypatch.setenv("FDTD_REV_STEPS", str(steps))
+    say("launch orders", case, "steps per sweep", steps)
     outs = []
     for order in ("1", "2"):
         monkeypatch.setenv("FDTD_TILE_ORDER", order)
