@@ -863,11 +863,20 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
         // H^{n-1/2} low faces), written before prim_rev of step n: E into its input
         // buffer FE (whose high-face E positions nothing else reads), H into its output
         // buffer FH
+        // one step per sweep: the x-face shell cells go to row 0 of their plane (ShellJob.xrow),
+        // where they fit when the face's rows fit in one row of the grid
+        const int xrow = (!two && g.P >= 2 && g.my <= g.nx) ? 1 : 0;
         auto shell_for = [&](int n, float* FE, float* FH) {
-            return ShellJob{FE, FH, store, interp_for(n, T, k, ip), n >= 1 ? interp_for(n - 1, T, k, ip) : none, 1,
-                            n >= 1 ? 1 : 0};
+            ShellJob j{FE, FH, store, interp_for(n, T, k, ip), n >= 1 ? interp_for(n - 1, T, k, ip) : none, 1,
+                       n >= 1 ? 1 : 0};
+            j.xrow = xrow;
+            return j;
         };
-        launch_inject_shell(g, ShellJob{Fp[0], Fp[0], store, none, interp_for(T - 1, T, k, ip), 0, 1}, q);   // H^{T-1/2}
+        {
+            ShellJob h{Fp[0], Fp[0], store, none, interp_for(T - 1, T, k, ip), 0, 1};   // H^{T-1/2}
+            h.xrow = xrow;
+            launch_inject_shell(g, h, q);
+        }
         if (!two) {
             launch_inject_shell(g, shell_for(T - 1, Fp[0], Fp[1]), q);
             for (int n = T - 1; n >= 0; --n) {
@@ -879,8 +888,8 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
                 // the interior reversal reads the E part of the shell from po; the adjoint launch
                 // then writes the shell of step n-1: E into pn (which the reversal has just
                 // written: the input of step n-1), H into po (which it has finished reading)
-                launch_prim_rev(g, rev, pl.box_o, pl.box_n, pl.rev_x0, po, pn, eps, ao, wave[n], mwave(n), grad_eps,
-                                q);
+                launch_prim_rev(g, rev, pl.box_o, pl.box_n, pl.rev_x0, xrow, po, pn, eps, ao, wave[n], mwave(n),
+                                grad_eps, q);
                 ShellJob next{};
                 if (n >= 1) next = shell_for(n - 1, pn, po);
                 launch_adj_step(g, adj, ao, an, eps, adj_psi, st & 1, n >= 1 ? &next : nullptr, q);
@@ -902,8 +911,8 @@ int fdtd_backward(const fdtd_problem_t* prob, const fdtd_store_cfg_t* cfg, const
                 launch_inject_shell(g, shell_for(T - 1, Fp[0], Fp[1]), q);
                 float* ao = Fa[0];
                 float* an = Fa[1];
-                launch_prim_rev(g, rev, pl.box_o, pl.box_n, pl.rev_x0, Fp[0], Fp[1], eps, ao, wave[n], mwave(n),
-                                grad_eps, q);
+                launch_prim_rev(g, rev, pl.box_o, pl.box_n, pl.rev_x0, xrow, Fp[0], Fp[1], eps, ao, wave[n],
+                                mwave(n), grad_eps, q);
                 ShellJob next{};
                 if (n >= 1) next = mid_for(n - 1);
                 launch_adj_step(g, adj, ao, an, eps, adj_psi, 0, n >= 1 ? &next : nullptr, q);

@@ -295,6 +295,7 @@ struct ShellJob {
     Interp qE, qH;
     int do_e, do_h;
     int slice;
+    int xrow;   // one-step reversal: x-face cells at position y - P of row 0 of their plane
 };
 
 // Compile-time storage type versions (the sweeps are instantiated per type so
@@ -504,7 +505,8 @@ void launch_rev2(const Grid& g, const Tiling& t, const float* F0, float* F1, con
                  float wave_n, float wave_n1, double* grad, float* stash, const float* mid, hipStream_t s);
 // step n-1's loss seed into the adjoint fields A (E then H) and its gradient term, from stash
 void launch_rev_pending(const Grid& g, float* A, double* grad, const float* stash, hipStream_t s);
-void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
+// xrow: the x-face shell cells sit at position y - P of row 0 of their plane (ShellJob.xrow)
+void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0, int xrow,
                      const float* F0, float* F1, const float* eps, float* Eb0, float wave, float mwave,
                      double* grad, hipStream_t s);
 // job (may be NULL): a shell written by trailing workgroups of the same launch

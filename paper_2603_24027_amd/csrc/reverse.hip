@@ -277,7 +277,11 @@ __device__ inline void shell_cell(const Grid& g, const ShellJob& j, int t) {
     }
     const long long N = g.N;
     float* A = high ? j.FE : j.FH + 3 * N;                    // E for the high faces, H for the low ones
-    const long long idx = f.x + (long long)g.nx * (f.y + (long long)g.ny * f.z);
+    // an x-face cell (y, z) one per row of its plane would cost a partial-line write per
+    // value; with xrow it goes to position y - P of row 0 of plane z instead (PML cells
+    // that the one-step reversal never reads otherwise), where a wave writes it contiguously
+    const long long idx = (j.xrow && f.blk % 6 == 0) ? (f.y - g.P) + (long long)g.nx * g.ny * f.z
+                                                    : f.x + (long long)g.nx * (f.y + (long long)g.ny * f.z);
     A[f.c0 * N + idx] = v0;
     A[f.c1 * N + idx] = v1;
 }
@@ -466,6 +470,7 @@ struct Box {            // the region prim_rev sweeps: I plus a one-cell shell
     int o[3];           // origin
     int n[3];           // extent
     int tx0;            // x origin of the tiles: o[0] rounded down to a 128-byte line
+    int xrow;           // x-face shell cells at position y - P of row 0 (ShellJob.xrow)
 };
 
 struct RevBufs {
@@ -735,8 +740,12 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
     if (c.pex >= 0) c.xcol = make_col(g, c.i0 + c.pex, c.j0 + c.pey);
     RevLanes Ln;
     // without wrap-around, idle lanes (outside the box) are never a neighbour of a box cell
-    Ln.h = lane_off(c.own.xy >= 0 && (c.live || g.periodic), c.own.xy);
-    Ln.r = lane_off(c.ring.xy >= 0, c.ring.xy);
+    // H of a column on the low x face (its interior rows) comes from row 0 with xrow
+    auto hface = [&](const Col& q) {
+        return bx.xrow && q.x == P - 1 && q.y >= P && q.y < g.ny - P ? q.y - P : q.xy;
+    };
+    Ln.h = lane_off(c.own.xy >= 0 && (c.live || g.periodic), hface(c.own));
+    Ln.r = lane_off(c.ring.xy >= 0, hface(c.ring));
     Ln.e = lane_off(xy_interior(g, c.own), c.own.xy);
     Ln.xe = lane_off(xy_interior(g, c.xcol), c.xcol.xy);
     Ln.src = src_lane(g, c.own);
@@ -747,8 +756,9 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_RE
         // interior in x and y, or on the x or y high face (the E^n shell in the input buffer)
         auto es = [&](const Col& q) {
             const bool iI = q.x >= P && q.x < g.nx - P, jI = q.y >= P && q.y < g.ny - P;
-            const bool face = P > 0 && ((q.x == g.nx - P && jI) || (q.y == g.ny - P && iI));
-            return lane_off(q.xy >= 0 && (xy_interior(g, q) || face), q.xy);
+            const bool xface = P > 0 && q.x == g.nx - P && jI;
+            const bool face = xface || (P > 0 && q.y == g.ny - P && iI);
+            return lane_off(q.xy >= 0 && (xy_interior(g, q) || face), bx.xrow && xface ? q.y - P : q.xy);
         };
         Ln.es = es(c.own);
         Ln.xes = es(c.xcol);
@@ -798,12 +808,13 @@ static void launch_prim_rev_t(const Grid& g, const Tiling& t, const Box& b, cons
                       Eb0, wave, mwave, grad);
 }
 
-void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0,
+void launch_prim_rev(const Grid& g, const Tiling& t, const int box_o[3], const int box_n[3], int tile_x0, int xrow,
                      const float* F0, float* F1, const float* eps, float* Eb0, float wave, float mwave, double* grad,
                      hipStream_t s) {
     Box b;
     for (int d = 0; d < 3; ++d) { b.o[d] = box_o[d]; b.n[d] = box_n[d]; }
     b.tx0 = tile_x0;
+    b.xrow = xrow;
     if (t.ty == 4 && t.cz == 4) launch_prim_rev_t<4, 4>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
     else if (t.ty == 4 && t.cz == 5) launch_prim_rev_t<4, 5>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);
     else if (t.ty == 4 && t.cz == 6) launch_prim_rev_t<4, 6>(g, t, b, F0, F1, eps, Eb0, wave, mwave, grad, s);

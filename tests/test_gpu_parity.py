@@ -437,6 +437,34 @@ def test_launch_orders_give_the_same_bits(case, steps, monkeypatch):
     assert abs(outs[1]["loss"] - L) <= 1e-5 * abs(L) and r <= 1e-4
 
 
+SHELL_GRIDS = {
+    # the one-step reversal puts the x-face shell cells into row 0 of their plane when
+    # P >= 2 and the face's rows fit in one grid row; these grids take either path
+    "pml2_rows_fit": lambda: w.tiny(n=(20, 18, 16), pml=2, steps=50),
+    "pml1_in_place": lambda: w.tiny(n=(14, 13, 12), pml=1, steps=50),
+    "tall_in_place": lambda: w.tiny(n=(16, 40, 16), pml=3, steps=50),
+}
+
+
+@pytest.mark.parametrize("case", list(SHELL_GRIDS))
+@pytest.mark.parametrize("dtype,k", [("fp32", 1), ("fp16", 3)])
+def test_interface_shell_layouts_against_oracle(case, dtype, k):
+    require_gpu()
+    prob = SHELL_GRIDS[case]()
+    say("interface shell layout", case, dtype, "k", k)
+    out = gpu_run(prob, dtype, k, keep_fields=False)
+    L, g = adjoint.grad_time_reversal(prob, ORACLE_MODE[dtype], k, match_fp32=True)
+    assert abs(out["loss"] - L) <= 1e-5 * abs(L)
+    r = rel(out["grad"], g)
+    cos = metrics.cosine_similarity(out["grad"], g)
+    cell = float(np.max(np.abs(out["grad"] - g)) / np.max(np.abs(g)))
+    say("  rel-L2 %.3e cosine %.12f per-cell %.3e" % (r, cos, cell))
+    if dtype == "fp32":
+        assert r <= 1e-4 and cell <= 1e-4
+    else:
+        assert cos >= 0.9999 and r <= 1e-2
+
+
 def test_graph_cache_eviction_with_calls_in_flight():
     """More distinct calls than the graph cache keeps, enqueued without synchronising:
     evicting a graph waits for its last launch, and every result equals the eager one."""
