@@ -729,14 +729,26 @@ int forward_with(const Plan& pl, const fdtd_problem_t* prob, const fdtd_store_cf
         // the two sweeps' tilings may meet the detector in different numbers of tiles
         launch_fill_f64(partials, (long long)T * pl.per_step, 0.0, q);
         int sw = 0, hc = 0, ec = 0;   // sweeps so far; PML copies holding the H-side and E-side auxiliaries
+        // One step per sweep and a storage type written directly: trailing workgroups of the
+        // sweeps record the kept steps, E^n of step n in sweep n (which reads it) and
+        // H^{n+1/2} in sweep n+1 (which reads the buffer sweep n wrote); the last step's H
+        // takes a launch of its own.  Otherwise the recorder launches after each kept step.
+        const bool trail = !two && !fp8;
+        auto slice_ptr = [&](int n) -> void* {
+            const int sl = n >= 0 ? slice_of(n) : -1;
+            return sl >= 0 ? (void*)((char*)store + (int64_t)sl * g.slice_stride) : nullptr;
+        };
         for (int n = 0; n < single; ++n, ++sw) {
             const float* in = F[(start + sw) & 1];
             float* out = F[(start + sw + 1) & 1];
-            launch_fwd_step(g, fwd, in, out, psi, hc, eps, wave[n], mwave(n), partials + (int64_t)n * pl.per_step, q);
+            const RecJob job{in, slice_ptr(n), slice_ptr(n - 1)};
+            launch_fwd_step(g, fwd, in, out, psi, hc, eps, wave[n], mwave(n), partials + (int64_t)n * pl.per_step,
+                            trail ? &job : nullptr, q);
             hc ^= 1;
             const int slice = slice_of(n);
-            if (slice >= 0) record(in, false, out, false, slice, q);
+            if (!trail && slice >= 0) record(in, false, out, false, slice, q);
         }
+        if (trail && single > 0) launch_record_job(g, RecJob{F[(start + sw) & 1], nullptr, slice_ptr(single - 1)}, q);
         for (int n = single; n + 1 < T; n += 2, ++sw) {
             const float* in = F[(start + sw) & 1];
             float* out = F[(start + sw + 1) & 1];

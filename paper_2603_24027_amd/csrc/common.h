@@ -480,8 +480,20 @@ void launch_put(void* dst, const void* host, long long n, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 struct Tiling;
+// Interface values of kept steps recorded from one field buffer F (E then H): E on the
+// high faces into the store's kept step dst_e, H on the low faces into dst_h (a null
+// destination skips that side).  Stored in the storage type directly (not for the
+// scaled FP8 type, which goes through the staging buffer and its own launches).
+struct RecJob {
+    const float* F;
+    void* dst_e;
+    void* dst_h;
+};
+// job (may be NULL): kept-step values recorded by trailing workgroups of the same launch
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                     const float* eps, float wave, float mwave, double* partials, hipStream_t s);
+                     const float* eps, float wave, float mwave, double* partials, const RecJob* job, hipStream_t s);
+// a RecJob as a launch of its own
+void launch_record_job(const Grid& g, const RecJob& job, hipStream_t s);
 // two forward steps n, n+1 in one sweep (PML copies: H side hcopy, E side ecopy in;
 // the other copies out); p0, p1: the two steps' detector partials; mid: NULL or the
 // buffer that receives the intermediate step's recorder values

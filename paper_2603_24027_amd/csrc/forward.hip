@@ -327,14 +327,56 @@ __device__ __forceinline__ double fwd_tile(const Grid& g, const FwdBufs& b, cons
 #ifndef FDTD_FWD_WAVES
 #define FDTD_FWD_WAVES 1
 #endif
+// One face cell and side of a RecJob: both tangential components from the field
+// buffer into the kept step, in its storage type.
+template <int DT>
+__device__ inline void rec_cell(const Grid& g, const RecJob& j, int t) {
+    const int face = g.my * g.mz + g.mx * g.mz + g.mx * g.my;   // < 2^31: 24 N < 2^31
+    if (t >= 2 * face) return;
+    const bool high = t >= face;
+    if (high) t -= face;
+    void* dst = high ? j.dst_e : j.dst_h;
+    if (!dst) return;
+    const FaceCell f = face_cell(g, t, high);
+    const long long N = g.N;
+    const float* A = high ? j.F : j.F + 3 * N;                 // E on the high faces, H on the low ones
+    const long long idx = f.x + (long long)g.nx * (f.y + (long long)g.ny * f.z);
+    store_code<DT>(dst, block_offset(g, f.blk) + f.u, A[f.c0 * N + idx]);
+    store_code<DT>(dst, block_offset(g, f.blk + 1) + f.u, A[f.c1 * N + idx]);
+}
+
+// the storage type is uniform over the launch: one branch per wave
+__device__ inline void rec_cell_any(const Grid& g, const RecJob& j, int t) {
+    switch (g.dtype) {
+        case 0: rec_cell<0>(g, j, t); break;
+        case 1: rec_cell<1>(g, j, t); break;
+        case 2: rec_cell<2>(g, j, t); break;
+        case 3: rec_cell<3>(g, j, t); break;
+        case 4: rec_cell<4>(g, j, t); break;
+        case 5: rec_cell<5>(g, j, t); break;
+        case 6: rec_cell<6>(g, j, t); break;
+        case 7: rec_cell<7>(g, j, t); break;
+        case 8: rec_cell<8>(g, j, t); break;
+        default: rec_cell<9>(g, j, t); break;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_record_job(Grid g, RecJob j) {
+    rec_cell_any(g, j, (int)blockIdx.x * 256 + (int)threadIdx.x);
+}
+
 template <int TY, int CZ, bool MS>
 __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MS ? 4 : FDTD_FWD_WAVES))) void k_fwd_step(
     Grid g, Tiling tl, const float* __restrict__ F0, float* __restrict__ F1, float* __restrict__ psi, int hcopy,
-    const float* __restrict__ eps, float wave, float mwave, double* __restrict__ partials) {
+    const float* __restrict__ eps, float wave, float mwave, double* __restrict__ partials, RecJob job) {
     __shared__ float sE[2][3][TY + 2][EXT];
     __shared__ float sH[3][TY + 1][TX + 1];
     __shared__ CoefTile<TY, CZ> ct;
     __shared__ double red[TY];
+    if ((int)blockIdx.x >= tl.count) {   // trailing workgroups: interface values of kept steps
+        rec_cell_any(g, job, ((int)blockIdx.x - tl.count) * (TX * TY) + (int)(threadIdx.y * TX + threadIdx.x));
+        return;
+    }
     const int L = logical_tile(tl);
     const int tix = L % tl.ntx, tiy = (L / tl.ntx) % tl.nty, tiz = L / (tl.ntx * tl.nty);
     FwdCtx<TY> c;
@@ -526,22 +568,35 @@ __global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ p
 
 template <int TY, int CZ>
 static void launch_fwd_step_t(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                              const float* eps, float wave, float mwave, double* partials, hipStream_t s) {
-    const dim3 grid(t.count), block(TX, TY);
+                              const float* eps, float wave, float mwave, double* partials, const RecJob* job,
+                              hipStream_t s) {
+    RecJob j{};
+    long long extra = 0;
+    if (job && g.P > 0 && g.vps > 0 && (job->dst_e || job->dst_h)) {
+        j = *job;
+        extra = (g.vps / 2 + TX * TY - 1) / (TX * TY);   // one thread per face cell and side
+    }
+    const dim3 grid((unsigned)(t.count + extra)), block(TX, TY);
     if (g.msrc_hi[0] > g.msrc_lo[0])
         launch_kernel(K_FWD_STEP, k_fwd_step<TY, CZ, true>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
-                      mwave, partials);
+                      mwave, partials, j);
     else
         launch_kernel(K_FWD_STEP, k_fwd_step<TY, CZ, false>, grid, block, s, g, t, F0, F1, psi, hcopy, eps, wave,
-                      mwave, partials);
+                      mwave, partials, j);
 }
 
 void launch_fwd_step(const Grid& g, const Tiling& t, const float* F0, float* F1, float* psi, int hcopy,
-                     const float* eps, float wave, float mwave, double* partials, hipStream_t s) {
-    if (t.ty == 4 && t.cz == 4) launch_fwd_step_t<4, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, s);
-    else if (t.ty == 4) launch_fwd_step_t<4, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, s);
-    else if (t.cz == 4) launch_fwd_step_t<8, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, s);
-    else launch_fwd_step_t<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, s);
+                     const float* eps, float wave, float mwave, double* partials, const RecJob* job, hipStream_t s) {
+    if (t.ty == 4 && t.cz == 4) launch_fwd_step_t<4, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, job, s);
+    else if (t.ty == 4) launch_fwd_step_t<4, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, job, s);
+    else if (t.cz == 4) launch_fwd_step_t<8, 4>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, job, s);
+    else launch_fwd_step_t<8, 8>(g, t, F0, F1, psi, hcopy, eps, wave, mwave, partials, job, s);
+}
+
+void launch_record_job(const Grid& g, const RecJob& job, hipStream_t s) {
+    if (g.P == 0 || g.vps == 0 || (!job.dst_e && !job.dst_h)) return;
+    const long long n = g.vps / 2;
+    launch_kernel(K_RECORD, k_record_job, dim3((unsigned)((n + 255) / 256)), dim3(256), s, g, job);
 }
 
 void launch_record(const Grid& g, const float* E, bool e_mid, const float* H, bool h_mid, void* store,
