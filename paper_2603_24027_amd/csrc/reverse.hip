@@ -431,8 +431,11 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(FDTD_AD
     c.hc.xy = -1;
     c.hc.x = c.hc.y = 0;
     c.hc.sx = c.hc.sy = -1;
-    if (c.tid < TX + TY) {
-        if (c.tid < TX) { c.hex = c.tid + 1; c.hey = 0; } else { c.hex = 0; c.hey = c.tid - TX + 1; }
+    // the halo cells: on waves 4-5 of an 8-row tile, so that no wave holds both ring and
+    // halo work (512x512x256: 916.8 -> 912.4 us), on waves 0-1 of a 4-row one
+    const int ht = TY == 8 ? c.tid - 4 * TX : c.tid;
+    if (ht >= 0 && ht < TX + TY) {
+        if (ht < TX) { c.hex = ht + 1; c.hey = 0; } else { c.hex = 0; c.hey = ht - TX + 1; }
         const int xr = c.i0 - 1 + c.hex, yr = c.j0 - 1 + c.hey;
         if (xr < g.nx && yr < g.ny) c.hc = make_col(g, xr, yr);
     }
