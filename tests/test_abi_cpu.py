@@ -75,6 +75,22 @@ def test_compression_factor_64x_on_slab_config():
     assert full / small == 64.0
 
 
+@pytest.mark.parametrize("name", ["c1", "c4", "c5", "ragged"])
+def test_workspace_does_not_depend_on_the_sweep_choice(name, monkeypatch):
+    # the caller sizes the workspace from store_config once; one or two steps per sweep
+    # (forward or reverse) and the launch order must all fit that same size
+    kw = {"steps": 9} if name in ("c4", "c5") else {}
+    p = pk.Problem(w.make(name, **kw))
+    ref = pk.store_config(p, "fp8_e4m3_scaled", 4).workspace_bytes
+    for env in ({"FDTD_FWD_STEPS": "1"}, {"FDTD_FWD_STEPS": "2"}, {"FDTD_REV_STEPS": "1"}, {"FDTD_REV_STEPS": "2"},
+                {"FDTD_TILE_ORDER": "1"}, {"FDTD_TILE_ORDER": "2"}):
+        for key, value in env.items():
+            monkeypatch.setenv(key, value)
+        assert pk.store_config(p, "fp8_e4m3_scaled", 4).workspace_bytes == ref, env
+        for key in env:
+            monkeypatch.delenv(key)
+
+
 def _call_forward(prob, dtype="fp32", k=1, interp=1):
     lib = pk.load()
     p = pk.Problem(prob)
