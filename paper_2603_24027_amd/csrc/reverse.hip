@@ -88,6 +88,43 @@ __device__ inline void hbar_new(const float (*cur)[TY + 2][EXT], const float (*n
     h[2] = h0[2] + (cur[0][ey][ex] - cur[0][ey + 1][ex]) + (cur[3][ey][ex] - cur[3][ey][ex + 1]);
 }
 
+// Tiles that reach no PML slab (class 0) keep three values per cell in the LDS planes
+// instead of six: the E-half terms there are (vx, -vx, vy, -vy, vz, -vz), kept as vx, vy,
+// vz in slots 0-2, and the H-half terms (-w0, w0, -w1, w1, -w2, w2), w = dt Hbar, kept as
+// w0, w1, w2.  The sums read them back with the same signs, so the results are the same
+// bits as with all six.
+template <int TY, int SL>
+__device__ __forceinline__ void put_g(float (*p)[TY + 2][EXT], int y, int x, const float o[6]) {
+    if constexpr (SL == 0) {
+        p[0][y][x] = o[0]; p[1][y][x] = o[2]; p[2][y][x] = o[4];
+    } else {
+        #pragma unroll
+        for (int t = 0; t < 6; ++t) p[t][y][x] = o[t];
+    }
+}
+
+template <int TY, int SL>
+__device__ __forceinline__ void put_gh(float (*p)[TY + 1][TX + 1], int y, int x, const float o[6]) {
+    if constexpr (SL == 0) {
+        p[0][y][x] = o[1]; p[1][y][x] = o[3]; p[2][y][x] = o[5];
+    } else {
+        #pragma unroll
+        for (int t = 0; t < 6; ++t) p[t][y][x] = o[t];
+    }
+}
+
+template <int TY, int SL>
+__device__ __forceinline__ void hbar_new_s(const float (*cur)[TY + 2][EXT], const float (*nxt)[TY + 2][EXT], int ex,
+                                           int ey, const float h0[3], float h[3]) {
+    if constexpr (SL == 0) {
+        h[0] = h0[0] + (cur[1][ey][ex] - nxt[1][ey][ex]) + ((-cur[2][ey][ex]) - (-cur[2][ey + 1][ex]));
+        h[1] = h0[1] + ((-cur[0][ey][ex]) - (-nxt[0][ey][ex])) + (cur[2][ey][ex] - cur[2][ey][ex + 1]);
+        h[2] = h0[2] + (cur[0][ey][ex] - cur[0][ey + 1][ex]) + ((-cur[1][ey][ex]) - (-cur[1][ey][ex + 1]));
+    } else {
+        hbar_new<TY>(cur, nxt, ex, ey, h0, h);
+    }
+}
+
 struct AdjBufs {
     rsrc_t A0, A1, eps, psi;   // adjoint fields in / out (Ebar then Hbar), both PML copies
     uint32_t pin, pout;        // byte offsets of the PML copies in / out
@@ -201,16 +238,14 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
         pp.zs = pp.zs && z1 >= 0;
         float o[6], po[6];
         ge_own<TY, CZ, SL>(dt, ct, lane + 1, row + 1, kk + 2, L.ysl, pp.zs, in.eb, in.ep, in.pe, o, po);
-        #pragma unroll
-        for (int t = 0; t < 6; ++t) sG[nxt][t][row + 1][lane + 1] = o[t];
+        put_g<TY, SL>(sG[nxt], row + 1, lane + 1, o);
         PsiLane l = L.po;                        // the block's own cells at k+1 only
         if (!own_next || z1 < 0) l.x = l.y = l.z = OOB;
         bst_psi_s<SL>(b.psi, l, pp, po);
         if (c.rlx >= 0) {
             ge_terms<SL>(dt, in.rb, in.rep, in.rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, kk + 2), o,
                          po);
-            #pragma unroll
-            for (int t = 0; t < 6; ++t) sG[nxt][t][c.rly][c.rlx] = o[t];
+            put_g<TY, SL>(sG[nxt], c.rly, c.rlx, o);
         }
     }
     __syncthreads();
@@ -220,7 +255,7 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
     float og[6];
     {
         float h[3], po[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        hbar_new<TY>(sG[cur], sG[nxt], lane + 1, row + 1, in.hb, h);
+        hbar_new_s<TY, SL>(sG[cur], sG[nxt], lane + 1, row + 1, in.hb, h);
         bst3v(b.A1, L.o, sk + 3 * nb, nb, h);
         og[0] = -dt * h[0]; og[1] = dt * h[0]; og[2] = -dt * h[1]; og[3] = dt * h[1]; og[4] = -dt * h[2];
         og[5] = dt * h[2];
@@ -229,27 +264,31 @@ __device__ __forceinline__ void adj_plane(const Grid& g, const AdjBufs& b, const
         if constexpr ((SL & 4) != 0) { if (pH.zs) gbar_axis(cf_z(ct, 1, kk + 1), 1, 2, og, in.ph, po); }
         if (!c.live) og[0] = og[1] = og[2] = og[3] = og[4] = og[5] = 0.0f;
         bst_psi_s<SL>(b.psi, L.po, pH, po);
-        #pragma unroll
-        for (int t = 0; t < 6; ++t) sGH[t][row + 1][lane + 1] = og[t];
+        put_gh<TY, SL>(sGH, row + 1, lane + 1, og);
     }
     if (c.hex >= 0) {
         float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (c.hc.xy >= 0) {
             float h[3], po[6];
-            hbar_new<TY>(sG[cur], sG[nxt], c.hex, c.hey, in.hhb, h);
+            hbar_new_s<TY, SL>(sG[cur], sG[nxt], c.hex, c.hey, in.hhb, h);
             o[0] = -dt * h[0]; o[1] = dt * h[0]; o[2] = -dt * h[1]; o[3] = dt * h[1]; o[4] = -dt * h[2];
             o[5] = dt * h[2];
             gbar_axes<SL>(cf_x(ct, 1, c.hex), cf_y(ct, 1, c.hey), cf_z(ct, 1, kk + 1), o, in.phh, po);
         }
-        #pragma unroll
-        for (int t = 0; t < 6; ++t) sGH[t][c.hey][c.hex] = o[t];
+        put_gh<TY, SL>(sGH, c.hey, c.hex, o);
     }
     __syncthreads();
     // ---- Ebar at plane k: Ex <- terms 2 (z), 5 (y); Ey <- 1 (z), 4 (x); Ez <- 0 (y), 3 (x) ----
     float e[3];
-    e[0] = ebc[0] + (g2p - og[2]) + (sGH[5][row][lane + 1] - og[5]);
-    e[1] = ebc[1] + (g1p - og[1]) + (sGH[4][row + 1][lane] - og[4]);
-    e[2] = ebc[2] + (sGH[0][row][lane + 1] - og[0]) + (sGH[3][row + 1][lane] - og[3]);
+    if constexpr (SL == 0) {   // slots w0, w1, w2: term 5 = w2, 4 = -w2, 0 = -w0, 3 = w1
+        e[0] = ebc[0] + (g2p - og[2]) + (sGH[2][row][lane + 1] - og[5]);
+        e[1] = ebc[1] + (g1p - og[1]) + ((-sGH[2][row + 1][lane]) - og[4]);
+        e[2] = ebc[2] + ((-sGH[0][row][lane + 1]) - og[0]) + (sGH[1][row + 1][lane] - og[3]);
+    } else {
+        e[0] = ebc[0] + (g2p - og[2]) + (sGH[5][row][lane + 1] - og[5]);
+        e[1] = ebc[1] + (g1p - og[1]) + (sGH[4][row + 1][lane] - og[4]);
+        e[2] = ebc[2] + (sGH[0][row][lane + 1] - og[0]) + (sGH[3][row + 1][lane] - og[3]);
+    }
     bst3v(b.A1, L.o, sk, nb, e);
     g1p = og[1];
     g2p = og[2];
@@ -339,25 +378,21 @@ __device__ __forceinline__ void adj_tile(const Grid& g, const AdjBufs& b, const 
         load_adj_in<TY, SL>(g, b, Ln, c, k0, pin[0]);
         float o[6], po[6];
         ge_terms<SL>(dt, eb, ep, pe, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, 0), o, po);
-        #pragma unroll
-        for (int t = 0; t < 6; ++t) sG[0][t][row + 1][lane + 1] = o[t];
+        put_g<TY, SL>(sG[0], row + 1, lane + 1, o);
         ge_terms<SL>(dt, eb0, ep0, pe0, cf_x(ct, 0, lane + 1), cf_y(ct, 0, row + 1), cf_z(ct, 0, 1), o, po);
-        #pragma unroll
-        for (int t = 0; t < 6; ++t) sG[1][t][row + 1][lane + 1] = o[t];
+        put_g<TY, SL>(sG[1], row + 1, lane + 1, o);
         // the own cell's E-side auxiliaries at k0 belong to this block
         bst_psi_s<SL>(b.psi, Ln.po, psi_plane(g, 1, z0, b.pout), po);
         if (c.rlx >= 0) {
             ge_terms<SL>(dt, rb, rep, rpe, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, 0), o, po);
-            #pragma unroll
-            for (int t = 0; t < 6; ++t) sG[0][t][c.rly][c.rlx] = o[t];
+            put_g<TY, SL>(sG[0], c.rly, c.rlx, o);
             ge_terms<SL>(dt, rb0, rep0, rpe0, cf_x(ct, 0, c.rlx), cf_y(ct, 0, c.rly), cf_z(ct, 0, 1), o, po);
-            #pragma unroll
-            for (int t = 0; t < 6; ++t) sG[1][t][c.rly][c.rlx] = o[t];
+            put_g<TY, SL>(sG[1], c.rly, c.rlx, o);
         }
         ebc[0] = eb0[0]; ebc[1] = eb0[1]; ebc[2] = eb0[2];
         __syncthreads();
         float h[3];
-        hbar_new<TY>(sG[0], sG[1], lane + 1, row + 1, hb, h);
+        hbar_new_s<TY, SL>(sG[0], sG[1], lane + 1, row + 1, hb, h);
         o[0] = -dt * h[0]; o[1] = dt * h[0]; o[2] = -dt * h[1]; o[3] = dt * h[1]; o[4] = -dt * h[2]; o[5] = dt * h[2];
         gbar_axes<SL>(cf_x(ct, 1, lane + 1), cf_y(ct, 1, row + 1), cf_z(ct, 1, 0), o, ph, po);
         g1p = pro ? o[1] : 0.0f;
